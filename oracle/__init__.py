@@ -1,0 +1,229 @@
+"""CPU oracle for the concurrent-queue hot path.  TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this package.  It shares no code with the HIP queues: it loads its
+own C library (gq_oracle.c, built with gcc by ``build()``) and a pure-Python
+exhaustive linearizability search (linearize.py).
+
+What it checks is the paper's correctness statement: histories are
+linearizable with respect to the sequential FIFO model (Section IV), and every
+token is delivered exactly once and in per-producer order (Section IV, device
+FIFO conformance).  BFS levels are checked against a sequential queue BFS
+(Section V-B).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+from .linearize import check_linearizable  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gq_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OP_ENQ, OP_DEQ = 0, 1
+ST_OK, ST_EMPTY, ST_FULL = 0, 1, 2
+
+
+def build() -> str:
+    """Compile the oracle's C part with gcc (always rebuilds)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-pthread",
+           _SRC, "-o", _LIB + ".tmp"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        U64 = ctypes.c_uint64
+        L.orc_fifo_replay.restype = ctypes.c_int64
+        L.orc_fifo_replay.argtypes = [U64, P, P, U64, U64, P, P, P, P]
+        L.orc_conservation.restype = ctypes.c_int
+        L.orc_conservation.argtypes = [U64, P, U64, P, P]
+        L.orc_producer_order.restype = ctypes.c_int
+        L.orc_producer_order.argtypes = [U64, P, P, P, P, P, P, ctypes.c_uint32, P]
+        L.orc_violation_scan.restype = ctypes.c_int
+        L.orc_violation_scan.argtypes = [U64, P, P, P, P, P, U64, P, U64, P, U64, P]
+        L.orc_bfs.restype = ctypes.c_int64
+        L.orc_bfs.argtypes = [U64, P, P, ctypes.c_uint32, P, P]
+        L.orc_locked_queue_run.restype = ctypes.c_int
+        L.orc_locked_queue_run.argtypes = [ctypes.c_uint32, U64, P, U64, U64, P,
+                                           ctypes.POINTER(ctypes.c_double)]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data) if a.size else ctypes.c_void_p(0)
+
+
+def _u64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint64))
+
+
+def _u8(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint8))
+
+
+# ----------------------------------------------------------------------------
+# History container
+# ----------------------------------------------------------------------------
+@dataclass
+class History:
+    """Struct-of-arrays history, grouped by proc, program order inside a proc."""
+    proc: np.ndarray   # uint32
+    op: np.ndarray     # uint8  (0 enq, 1 deq)
+    st: np.ndarray     # uint8  (0 OK, 1 EMPTY, 2 FULL)
+    val: np.ndarray    # uint64
+    call: np.ndarray   # uint64
+    ret: np.ndarray    # uint64
+
+    def __post_init__(self):
+        self.proc = np.ascontiguousarray(self.proc, dtype=np.uint32)
+        self.op = _u8(self.op)
+        self.st = _u8(self.st)
+        self.val = _u64(self.val)
+        self.call = _u64(self.call)
+        self.ret = _u64(self.ret)
+
+    def __len__(self):
+        return int(self.op.shape[0])
+
+    @staticmethod
+    def from_rows(rows):
+        """rows: iterable of (proc, op, st, val, call, ret)."""
+        rows = list(rows)
+        if not rows:
+            z = np.zeros(0)
+            return History(z, z, z, z, z, z)
+        cols = list(zip(*rows))
+        return History(*[np.array(c) for c in cols])
+
+    def sorted_by_proc(self) -> "History":
+        """Stable reorder so each proc's ops are contiguous (keeps order)."""
+        o = np.argsort(self.proc, kind="stable")
+        return History(self.proc[o], self.op[o], self.st[o], self.val[o],
+                       self.call[o], self.ret[o])
+
+    def enq_ok(self):
+        return self.val[(self.op == OP_ENQ) & (self.st == ST_OK)]
+
+    def deq_ok(self):
+        return self.val[(self.op == OP_DEQ) & (self.st == ST_OK)]
+
+
+# ----------------------------------------------------------------------------
+# O1/O2 sequential replay
+# ----------------------------------------------------------------------------
+def fifo_replay(ops, args, capacity: int = 0, prefill=()):
+    """Replay a total order through the bounded sequential FIFO.
+
+    Returns (status uint8[m], values uint64[m], residual uint64[]).
+    """
+    op = _u8(ops)
+    arg = _u64(args)
+    pre = _u64(prefill)
+    m = op.shape[0]
+    st = np.zeros(m, dtype=np.uint8)
+    val = np.zeros(m, dtype=np.uint64)
+    resid = np.zeros(m + pre.shape[0] + 1, dtype=np.uint64)
+    n = lib().orc_fifo_replay(m, _p(op), _p(arg), capacity, pre.shape[0], _p(pre),
+                              _p(st), _p(val), _p(resid))
+    if n < 0:
+        raise MemoryError("orc_fifo_replay")
+    return st, val, resid[:n].copy()
+
+
+# ----------------------------------------------------------------------------
+# O3 conservation
+# ----------------------------------------------------------------------------
+def conservation(put_in, taken_out):
+    """Returns dict(lost, extra, dup_in); all zero iff the multisets match."""
+    a = _u64(put_in)
+    b = _u64(taken_out)
+    out = np.zeros(3, dtype=np.uint64)
+    rc = lib().orc_conservation(a.shape[0], _p(a), b.shape[0], _p(b), _p(out))
+    if rc < 0:
+        raise MemoryError("orc_conservation")
+    return {"lost": int(out[0]), "extra": int(out[1]), "dup_in": int(out[2])}
+
+
+# ----------------------------------------------------------------------------
+# O4 per-producer order
+# ----------------------------------------------------------------------------
+def producer_order(h: History, shift: int = 32):
+    out = np.zeros(3, dtype=np.uint64)
+    rc = lib().orc_producer_order(len(h), _p(h.proc), _p(h.op), _p(h.st), _p(h.val),
+                                  _p(h.call), _p(h.ret), shift, _p(out))
+    if rc < 0:
+        raise MemoryError("orc_producer_order")
+    return {"consumer_order": int(out[0]), "realtime_order": int(out[1]),
+            "deq_before_enq": int(out[2])}
+
+
+# ----------------------------------------------------------------------------
+# O6 violation scan
+# ----------------------------------------------------------------------------
+VIOLATIONS = ("fresh", "repeat", "order", "witness", "witness_count", "full", "loss")
+
+
+def violation_scan(h: History, prefill=(), drain=(), capacity: int = 0):
+    pre = _u64(prefill)
+    dr = _u64(drain)
+    out = np.zeros(7, dtype=np.uint64)
+    rc = lib().orc_violation_scan(len(h), _p(h.op), _p(h.st), _p(h.val), _p(h.call),
+                                  _p(h.ret), pre.shape[0], _p(pre), dr.shape[0], _p(dr),
+                                  capacity, _p(out))
+    if rc < 0:
+        raise MemoryError("orc_violation_scan")
+    return {k: int(v) for k, v in zip(VIOLATIONS, out)}
+
+
+def all_zero(d: dict) -> bool:
+    return all(v == 0 for v in d.values())
+
+
+# ----------------------------------------------------------------------------
+# O7 BFS
+# ----------------------------------------------------------------------------
+def bfs(offsets, cols, root: int):
+    """Returns (levels uint32[nv], n_levels, edges_scanned)."""
+    off = _u64(offsets)
+    c = np.ascontiguousarray(np.asarray(cols, dtype=np.uint32))
+    nv = off.shape[0] - 1
+    lvl = np.zeros(nv, dtype=np.uint32)
+    scanned = np.zeros(1, dtype=np.uint64)
+    nl = lib().orc_bfs(nv, _p(off), _p(c), root, _p(lvl), _p(scanned))
+    if nl < 0:
+        raise ValueError("orc_bfs failed")
+    return lvl, int(nl), int(scanned[0])
+
+
+# ----------------------------------------------------------------------------
+# Host locked-queue baseline
+# ----------------------------------------------------------------------------
+def locked_queue_run(roles: np.ndarray, capacity: int, prefill: int):
+    """roles: uint8 [threads, ops]. Returns (ok_enq, ok_deq, seconds)."""
+    r = _u8(roles)
+    threads, ops = r.shape
+    out = np.zeros(2, dtype=np.uint64)
+    sec = ctypes.c_double(0.0)
+    rc = lib().orc_locked_queue_run(threads, ops, _p(r), capacity, prefill, _p(out),
+                                    ctypes.byref(sec))
+    if rc != 0:
+        raise MemoryError("orc_locked_queue_run")
+    return int(out[0]), int(out[1]), float(sec.value)
