@@ -1,0 +1,234 @@
+"""Throughput benchmark of the MI355X queues (one GPU).
+
+Workload (the throughput sweep's headline point): a queue of capacity 2^20
+with uint64 payloads, prefilled to n/2 outside the timed region; one step is
+2^26 operation attempts by 2048 workgroups x 256 lanes (128 per lane), each op
+an enqueue or a dequeue with probability 1/2 drawn from the seeded SplitMix64
+stream, tried once.  Throughput = (successful enqueues + successful dequeues)
+/ time (the paper's successful-operation throughput, Section V-A).  The
+queue is not reset between steps: at a 50/50 mix its size stays near n/2.
+
+Prints one JSON line.  Also measured in the same run: the atomic/bandwidth
+roofline probes (same-address FAA rate, distinct-line CAS rate, HBM copy
+bandwidth) and the CPU baselines (the oracle's sequential replay of the same
+operation stream, and a host mutex-protected ring on all host cores).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+CAP = 1 << 20
+LANES = 2048 * 256
+OPS_PER_LANE = 128          # 2^26 attempts per step
+ITEM_BYTES = 8
+# Algorithmic bytes per successful operation of the outer queue's fast path:
+# two slot RMWs (8 B each, counted read + write), two slot loads, two
+# threshold loads, one payload access (see the design notes).
+BYTES_PER_OP = 2 * 16 + 2 * 8 + 2 * 8 + ITEM_BYTES
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def measure_probes(gq, torch):
+    """Roofline probes: R_ctr (same-address FAA), R_slot (distinct-line CAS),
+    HBM copy bandwidth.  Each is timed with events on the current stream."""
+    res = {}
+    ctr = torch.zeros(64, dtype=torch.int64, device="cuda")
+
+    def timed(fn, reps=3):
+        best = None
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        return best
+
+    lanes, iters = 2048 * 256, 64
+    gq.probe_faa(ctr, lanes, 4, False)
+    ms = timed(lambda: gq.probe_faa(ctr, lanes, iters, False))
+    res["r_ctr_wave_faa_per_s"] = (lanes // 64) * iters / (ms * 1e-3)
+    ms = timed(lambda: gq.probe_faa(ctr, 256 * 256, 16, True))
+    res["r_ctr_lane_faa_per_s"] = 256 * 256 * 16 / (ms * 1e-3)
+    nslots = 2 * CAP
+    slots = torch.zeros(nslots, dtype=torch.int64, device="cuda")
+    gq.probe_cas(slots, nslots, 8, lanes, 2)
+    ms = timed(lambda: gq.probe_cas(slots, nslots, 8, lanes, 16))
+    res["r_slot_cas_per_s"] = lanes * 16 / (ms * 1e-3)
+    del slots
+    n = 1 << 28  # 2 GiB per buffer
+    src = torch.ones(n, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    gq.probe_copy(dst, src, n)
+    ms = timed(lambda: gq.probe_copy(dst, src, n))
+    res["hbm_copy_gbs"] = 2 * n * 8 / (ms * 1e-3) / 1e9
+    del src, dst
+    return res
+
+
+def cpu_baselines(seed, sample_lanes):
+    """Oracle replay (1 core) on a bounded sample of the same op stream, and
+    the host locked queue on all host cores."""
+    import oracle
+    import workloads
+    roles = workloads.mix_roles(seed, sample_lanes, OPS_PER_LANE)
+    toks = workloads.mix_tokens(roles)
+    pre = np.arange(1, CAP // 2 + 1, dtype=np.uint64) | np.uint64(0xFFFFFFFF << 32)
+    t0 = time.perf_counter()
+    st, _, _ = oracle.fifo_replay(roles.ravel(), toks.ravel(), capacity=CAP, prefill=pre)
+    dt = time.perf_counter() - t0
+    ok = int((st == 0).sum())
+    replay = {"value": ok / dt / 1e6, "unit": "Mops/s", "cores": 1, "kind": "oracle",
+              "sample": f"sequential FIFO replay of {sample_lanes} lanes x {OPS_PER_LANE} ops "
+                        f"of the same 50/50 stream in lane-major order, capacity 2^20, "
+                        f"prefill n/2 ({roles.size} ops, {dt:.2f} s)"}
+    cores = os.cpu_count() or 1
+    threads = min(cores, 64)
+    lroles = workloads.mix_roles(seed + 1, threads, 1 << 18)
+    oke, okd, sec = oracle.locked_queue_run(lroles, CAP, CAP // 2)
+    locked = {"value": (oke + okd) / sec / 1e6, "unit": "Mops/s", "cores": threads,
+              "kind": "host mutex + ring",
+              "sample": f"{threads} threads x 2^18 ops, 50/50 mix, capacity 2^20, prefill n/2"}
+    return replay, locked
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--kind", default="lfq", choices=["lfq"])
+    ap.add_argument("--slot-mode", default="remap", choices=["remap", "padded"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-probes", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2606_01693_amd as gq
+    import workloads
+
+    torch.cuda.set_device(0)
+    info = gq.device_info()
+    log(f"[bench] device {info}")
+    q = gq.Queue(args.kind, CAP, item_width=ITEM_BYTES, max_threads=LANES,
+                 slot_mode=args.slot_mode)
+    pre = torch.arange(1, CAP // 2 + 1, dtype=torch.int64, device="cuda") | (0xFFFFFFFF << 32)
+    q.enqueue_batch(pre)
+    counts = torch.zeros(4, dtype=torch.int64, device="cuda")
+    base_seed = workloads.run_seed(2, 0)
+    step = 0
+    for _ in range(args.warmup):
+        q.run_mix(base_seed + step, LANES, OPS_PER_LANE, counts)
+        step += 1
+    torch.cuda.synchronize()
+    assert q.check_error() == gq.GQ_OK
+    counts.zero_()
+    events = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        q.run_mix(base_seed + step, LANES, OPS_PER_LANE, counts)
+        e1.record()
+        events.append((e0, e1))
+        step += 1
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    err = q.check_error()
+    if err != gq.GQ_OK:
+        raise SystemExit(f"device error {gq.status_str(err)}")
+    c = counts.cpu().tolist()
+    ok_ops = c[0] + c[1]
+    wall = t1 - t0
+    kernel_ms = [a.elapsed_time(b) for a, b in events]
+    kavg = float(np.mean(kernel_ms))
+    value = ok_ops / wall / 1e6
+    per_launch_ok = ok_ops / args.steps
+    achieved_gbs = per_launch_ok * BYTES_PER_OP / (kavg * 1e-3) / 1e9
+    log(f"[bench] counts ok_enq={c[0]} ok_deq={c[1]} full={c[2]} empty={c[3]} "
+        f"kernel_ms={kernel_ms}")
+    stats = q.stats()
+
+    out = {
+        "metric": "Mops/s enq+deq at 50/50 mix, 2^20-slot queue",
+        "value": value,
+        "unit": "Mops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"G-LFQ ({args.kind}) mixed 50/50, capacity 2^20, uint64 payload, "
+                        f"2^26 op attempts per step, 2048 WGs x 256 lanes, prefill n/2, "
+                        f"slots={args.slot_mode}",
+            "capacity": CAP, "lanes": LANES, "ops_per_lane": OPS_PER_LANE,
+            "parallelism": "single GPU",
+        },
+        "kernel_ms_avg": kavg,
+        "ok_ops_per_step": per_launch_ok,
+        "full_per_step": c[2] / args.steps,
+        "empty_per_step": c[3] / args.steps,
+        "cas_fail_per_ok_op": stats.cas_fail / max(1, stats.ok_enq + stats.ok_deq + ok_ops),
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved_gbs / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "k_mix<G-LFQ>",
+            "bytes_per_ok_op": BYTES_PER_OP,
+        },
+    }
+    if not args.no_probes:
+        p = measure_probes(gq, torch)
+        # Each of the four ticket counters serves one of every two operations
+        # (enqueues: fq.Head, aq.Tail; dequeues: aq.Head, fq.Tail), and one
+        # WaveFAA covers the a lanes of a wave taking the same branch (a = 32
+        # at a 50/50 mix).  Each successful op performs 2 slot RMWs.
+        a = 32.0
+        bound_ops = min(2 * a * p["r_ctr_wave_faa_per_s"],
+                        p["r_slot_cas_per_s"] / 2.0,
+                        p["hbm_copy_gbs"] * 1e9 / BYTES_PER_OP)
+        out["atomic_roofline"] = dict(p, bound_mops=bound_ops / 1e6,
+                                      frac=(per_launch_ok / (kavg * 1e-3)) / bound_ops)
+    if not args.no_cpu:
+        replay, locked = cpu_baselines(base_seed, 1 << 17)
+        out["cpu_baseline"] = replay
+        out["cpu_locked_queue"] = locked
+        out["host"] = {"cpu": platform.processor() or platform.machine(),
+                       "cores": os.cpu_count()}
+    q.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,115 @@
+/*
+ * gq_bench.h -- workload drivers and roofline probes of libgq.so (C ABI).
+ *
+ * These entry points launch the paper's benchmark shapes on a queue created
+ * with gq.h, optionally recording a per-operation history for the
+ * linearizability checks (Section IV: fields proc, op, arg/ret, call, end).
+ * Same conventions as gq.h: device pointers are caller-owned, calls are
+ * stream-ordered and asynchronous, status codes are returned.
+ *
+ * Per-operation randomness is the counter-based SplitMix64 stream
+ * r(seed, c) = mix(seed + (c + 1) * 0x9E3779B97F4A7C15) with
+ * c = (lane << 32) | draw, evaluated on the device.
+ */
+#ifndef GQ_BENCH_H
+#define GQ_BENCH_H
+
+#include <stdint.h>
+
+#include "gq.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* History buffers (device memory).  Lane g's r-th operation is stored at
+ * g * per_lane + r while r < per_lane; further operations are executed but not
+ * stored.  count[g] receives the number of operations lane g executed.
+ * opst = op | (status << 1), op 0 = enqueue, 1 = dequeue; status as gq_status.
+ * val is the enqueued argument or the dequeued value (0 for EMPTY).
+ * call/ret are device real-time stamps (100 MHz) taken before the call and
+ * after the operation's writes completed.                                     */
+typedef struct gq_history {
+    uint64_t *val;
+    uint64_t *call;
+    uint64_t *ret;
+    uint8_t *opst;
+    uint32_t *count;
+    uint32_t per_lane;
+    uint32_t reserved;
+} gq_history;
+
+/* Mixed workload (Section V-A micro-benchmark shape, fixed op count): each of
+ * `lanes` lanes (a multiple of 256, launched as lanes/256 workgroups of 256)
+ * performs ops_per_lane operations; op r of lane g is an enqueue when the top
+ * bit of r(seed, (g << 32) | r) is 0, else a dequeue.  Each op is tried once:
+ * FULL/EMPTY outcomes are counted, not retried.  Lane g's j-th successful
+ * enqueue carries the token (g << 32) | (j + 1) (Section IV token format).
+ * d_counts[4] += {ok_enq, ok_deq, full, empty}.  hist may be NULL.            */
+gq_status gq_run_mix(gq_queue *q, uint64_t seed, uint32_t lanes, uint32_t ops_per_lane,
+                     uint64_t *d_counts, const gq_history *hist, void *stream);
+
+/* Balanced workload (Section V-A "balanced kernel", fixed op count): every
+ * lane performs `rounds` times (enqueue its next token; dequeue), each tried
+ * once.  Tokens as in gq_run_mix.  d_counts[4] as above.                      */
+gq_status gq_run_balanced(gq_queue *q, uint32_t lanes, uint32_t rounds, uint64_t *d_counts,
+                          const gq_history *hist, void *stream);
+
+/* Producer/consumer workload (Section V-A "split kernel" shape with retries):
+ * d_lane_role[g] = 0 marks lane g a producer, 1 a consumer.  Each producer
+ * enqueues items_per_producer tokens, retrying on FULL; consumers retry on
+ * EMPTY until `target` items were taken in total.  In round r lane g is
+ * active iff r(seed, (g << 32) | r) >> (64 - log2_inv_p) == 0 (always when
+ * log2_inv_p == 0).  token_mode 0: (g << 32) | (seq + 1); token_mode 1:
+ * (g << 20) | seq (32-bit payloads).  Producers and consumers wait for each
+ * other, so all lanes must be co-resident (GQ_ERR_RESIDENCY otherwise).
+ * jitter > 0 adds a seeded pause of up to `jitter` sleep units per round.
+ * max_rounds bounds every lane's loop; exceeding it latches GQ_ERR_DEVICE.
+ * d_counts[4] += {ok_enq, ok_deq, full, empty}.                               */
+gq_status gq_run_prodcons(gq_queue *q, uint64_t seed, uint32_t lanes, uint32_t block,
+                          const uint8_t *d_lane_role, uint32_t items_per_producer,
+                          uint64_t target, uint32_t log2_inv_p, uint32_t token_mode,
+                          uint32_t jitter, uint64_t max_rounds, uint64_t *d_counts,
+                          const gq_history *hist, void *stream);
+
+/* Scripted run for small linearizability tests: lane g (of `lanes`, one
+ * workgroup of `block` lanes per `lanes_per_block` active lanes) executes
+ * n_ops[g] operations from ops[g * max_ops ...] (0 enqueue, 1 dequeue) with
+ * arguments args[...], pausing pause[g * max_ops + r] sleep units before op r.
+ * Results go to hist (required).  Lanes are spread one per wavefront when
+ * spread != 0, so that they really run concurrently.                          */
+gq_status gq_run_script(gq_queue *q, uint32_t lanes, uint32_t spread, const uint8_t *d_ops,
+                        const uint64_t *d_args, const uint16_t *d_pause,
+                        const uint32_t *d_n_ops, uint32_t max_ops, const gq_history *hist,
+                        void *stream);
+
+/* ---- roofline probes -------------------------------------------------------
+ * R_ctr: lanes/64 wavefronts each perform `iters` fetch-and-adds on the single
+ *   counter *d_ctr: one per wavefront (per_lane = 0, the WaveFAA shape) or one
+ *   per lane (per_lane = 1).
+ * R_slot: each lane performs `iters` 64-bit CAS on slot (t mod nslots), t from
+ *   a per-lane ticket sequence, slots spaced stride_bytes apart.
+ * Copy: d_dst[i] = d_src[i] for n 64-bit words (HBM stream bandwidth).
+ * Fence: each wavefront performs `iters` agent-scope release+acquire fences
+ *   around one relaxed atomic store to its own line.                          */
+gq_status gq_probe_faa(uint64_t *d_ctr, uint32_t lanes, uint32_t iters, uint32_t per_lane,
+                       void *stream);
+gq_status gq_probe_cas(uint64_t *d_slots, uint64_t nslots, uint32_t stride_bytes,
+                       uint32_t lanes, uint32_t iters, void *stream);
+gq_status gq_probe_copy(uint64_t *d_dst, const uint64_t *d_src, uint64_t n, void *stream);
+gq_status gq_probe_fence(uint64_t *d_lines, uint32_t lanes, uint32_t iters, uint32_t mode,
+                         void *stream);
+
+/* Number of workgroups of `block` lanes that can be resident at once for the
+ * given driver kernel ("mix", "prodcons"), summed over all compute units.     */
+gq_status gq_resident_blocks(const char *kernel, gq_kind kind, uint32_t block,
+                             uint32_t *out_blocks);
+
+/* Device properties used by the benchmark: compute units, wavefront size,
+ * and the device's name (gcnArchName) copied into name[0..len).               */
+gq_status gq_device_info(uint32_t *cus, uint32_t *wave, char *name, uint32_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GQ_BENCH_H */

@@ -1,0 +1,334 @@
+"""ctypes binding of libgq.so (include/gq.h, include/gq_bench.h).
+
+Argument marshalling only: every queue operation runs in the HIP kernels of
+libgq.so.  PyTorch provides device memory (``torch.empty(..., device="cuda")``)
+and the current HIP stream; nothing else.  There is no CPU fallback: if the
+library is missing this module raises at import.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgq.so")
+
+GQ_OK, GQ_EMPTY, GQ_FULL = 0, 1, 2
+GQ_ERR_INVALID, GQ_ERR_NOMEM, GQ_ERR_HIP, GQ_ERR_RESIDENCY = -1, -2, -3, -4
+GQ_ERR_CYCLE_BOUND, GQ_ERR_POOL_EXHAUSTED, GQ_ERR_DEVICE = -5, -6, -7
+
+KINDS = {"lfq": 0, "wfq": 1, "ymc": 2}
+SLOT_MODES = {"remap": 0, "padded": 1}
+
+# Every symbol include/gq.h and include/gq_bench.h declare.
+EXPORTS = (
+    "gq_required_bytes", "gq_create", "gq_destroy", "gq_reset", "gq_enqueue_batch",
+    "gq_dequeue_batch", "gq_device_view", "gq_read_stats", "gq_clear_stats",
+    "gq_check_error", "gq_status_str", "gq_run_mix", "gq_run_balanced", "gq_run_prodcons",
+    "gq_run_script", "gq_probe_faa", "gq_probe_cas", "gq_probe_copy", "gq_probe_fence",
+    "gq_resident_blocks", "gq_device_info",
+)
+
+
+class GQError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)} ({status})")
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("slot_mode", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+                ("ymc_pool_cells", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("reserved1", ctypes.c_uint32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in
+                ("ok_enq", "ok_deq", "full", "empty", "cas_fail", "tickets", "slow_enter",
+                 "helps")]
+
+
+class _History(ctypes.Structure):
+    _fields_ = [("val", ctypes.c_void_p), ("call", ctypes.c_void_p), ("ret", ctypes.c_void_p),
+                ("opst", ctypes.c_void_p), ("count", ctypes.c_void_p),
+                ("per_lane", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class _RingView(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_void_p), ("head", ctypes.c_void_p), ("tail", ctypes.c_void_p),
+                ("threshold", ctypes.c_void_p), ("records", ctypes.c_void_p)]
+
+
+class _DevView(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("item_width", ctypes.c_uint32),
+                ("log2_cap", ctypes.c_uint32), ("slot_mode", ctypes.c_uint32),
+                ("max_threads", ctypes.c_uint32), ("pad0", ctypes.c_uint32),
+                ("capacity", ctypes.c_uint64), ("data", ctypes.c_void_p),
+                ("aq", _RingView), ("fq", _RingView), ("err", ctypes.c_void_p),
+                ("stats", ctypes.c_void_p), ("ymc_cells", ctypes.c_void_p),
+                ("ymc_pool_cells", ctypes.c_uint64), ("ymc_ctr", ctypes.c_void_p),
+                ("ymc_handles", ctypes.c_void_p)]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libgq.so not built at {path}; run __graft_entry__.build()")
+    # PyTorch ships its own HIP runtime.  Load it first so that libgq.so binds
+    # to that same runtime (its libamdhip64.so.7 dependency then resolves to
+    # the already-loaded copy); two runtimes in one process do not share
+    # devices, memory or streams.
+    import torch  # noqa: F401
+    L = ctypes.CDLL(path)
+    P, U32, U64, I32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    sig = {
+        "gq_required_bytes": [I32, U64, U32, U32, P, P],
+        "gq_create": [I32, U64, U32, U32, P, P, U64, P],
+        "gq_destroy": [P],
+        "gq_reset": [P, P],
+        "gq_enqueue_batch": [P, P, U64, P, P, P],
+        "gq_dequeue_batch": [P, P, U64, P, P, P],
+        "gq_device_view": [P, P],
+        "gq_read_stats": [P, P, P],
+        "gq_clear_stats": [P, P],
+        "gq_check_error": [P, P],
+        "gq_run_mix": [P, U64, U32, U32, P, P, P],
+        "gq_run_balanced": [P, U32, U32, P, P, P],
+        "gq_run_prodcons": [P, U64, U32, U32, P, U32, U64, U32, U32, U32, U64, P, P, P],
+        "gq_run_script": [P, U32, U32, P, P, P, P, U32, P, P],
+        "gq_probe_faa": [P, U32, U32, U32, P],
+        "gq_probe_cas": [P, U64, U32, U32, U32, P],
+        "gq_probe_copy": [P, P, U64, P],
+        "gq_probe_fence": [P, U32, U32, U32, P],
+        "gq_resident_blocks": [ctypes.c_char_p, I32, U32, P],
+        "gq_device_info": [P, P, P, U32],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.gq_status_str.argtypes = [ctypes.c_int]
+    L.gq_status_str.restype = ctypes.c_char_p
+    return L
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def status_str(s: int) -> str:
+    return lib().gq_status_str(int(s)).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != GQ_OK:
+        raise GQError(rc, what)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the queues run on the GPU only; no HIP device is visible")
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def required_bytes(kind: str, capacity: int, item_width: int = 8, max_threads: int = 1,
+                   slot_mode: str = "remap", ymc_pool_cells: int = 0) -> int:
+    o = _Options(SLOT_MODES[slot_mode], 0, ymc_pool_cells, 0, 0)
+    out = ctypes.c_uint64(0)
+    _check(lib().gq_required_bytes(KINDS[kind], capacity, item_width, max_threads,
+                                   ctypes.byref(o), ctypes.byref(out)), "gq_required_bytes")
+    return int(out.value)
+
+
+@dataclass
+class Stats:
+    ok_enq: int
+    ok_deq: int
+    full: int
+    empty: int
+    cas_fail: int
+    tickets: int
+    slow_enter: int
+    helps: int
+
+
+class History:
+    """Device history buffers for `lanes` lanes x `per_lane` records."""
+
+    def __init__(self, lanes: int, per_lane: int):
+        torch = _torch()
+        n = lanes * per_lane
+        self.lanes, self.per_lane = lanes, per_lane
+        self.val = torch.zeros(n, dtype=torch.int64, device="cuda")
+        self.call = torch.zeros(n, dtype=torch.int64, device="cuda")
+        self.ret = torch.zeros(n, dtype=torch.int64, device="cuda")
+        self.opst = torch.zeros(n, dtype=torch.uint8, device="cuda")
+        self.count = torch.zeros(lanes, dtype=torch.int32, device="cuda")
+
+    def c(self) -> _History:
+        return _History(self.val.data_ptr(), self.call.data_ptr(), self.ret.data_ptr(),
+                        self.opst.data_ptr(), self.count.data_ptr(), self.per_lane, 0)
+
+    def to_numpy(self):
+        """Returns (proc, op, st, val, call, ret, overflow) for the stored records,
+        grouped by lane in program order; overflow = lanes that executed more
+        operations than were stored."""
+        cnt = self.count.cpu().numpy().astype(np.int64)
+        stored = np.minimum(cnt, self.per_lane)
+        lane_start = np.repeat(np.arange(self.lanes, dtype=np.int64) * self.per_lane, stored)
+        within = np.arange(int(stored.sum()), dtype=np.int64) - \
+            np.repeat(np.cumsum(stored) - stored, stored)
+        idx = lane_start + within
+        proc = np.repeat(np.arange(self.lanes, dtype=np.uint32), stored)
+        opst = self.opst.cpu().numpy()[idx]
+        val = self.val.cpu().numpy().view(np.uint64)[idx]
+        call = self.call.cpu().numpy().view(np.uint64)[idx]
+        ret = self.ret.cpu().numpy().view(np.uint64)[idx]
+        return proc, (opst & 1).astype(np.uint8), (opst >> 1).astype(np.uint8), val, call, ret, \
+            int((cnt > self.per_lane).sum())
+
+
+class Queue:
+    """One device queue.  kind: 'lfq' | 'wfq' | 'ymc'."""
+
+    def __init__(self, kind: str, capacity: int, item_width: int = 8, max_threads: int = 1,
+                 slot_mode: str = "remap", ymc_pool_cells: int = 0):
+        torch = _torch()
+        self.kind, self.capacity, self.item_width = kind, capacity, item_width
+        self.max_threads = max_threads
+        nbytes = required_bytes(kind, capacity, item_width, max_threads, slot_mode, ymc_pool_cells)
+        # torch owns the memory; 256-byte alignment comes from the caching allocator
+        self._buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self._opts = _Options(SLOT_MODES[slot_mode], 0, ymc_pool_cells, 0, 0)
+        h = ctypes.c_void_p(0)
+        _check(lib().gq_create(KINDS[kind], capacity, item_width, max_threads,
+                               ctypes.byref(self._opts), _ptr(self._buf), nbytes,
+                               ctypes.byref(h)), "gq_create")
+        self._h = h
+        self.nbytes = nbytes
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gq_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def reset(self, stream=None):
+        _check(lib().gq_reset(self._h, _stream(stream)), "gq_reset")
+
+    def enqueue_batch(self, items, status=None, num_ok=None, stream=None):
+        _check(lib().gq_enqueue_batch(self._h, _ptr(items), items.numel(), _ptr(status),
+                                      _ptr(num_ok), _stream(stream)), "gq_enqueue_batch")
+
+    def dequeue_batch(self, out, status=None, num_ok=None, stream=None):
+        _check(lib().gq_dequeue_batch(self._h, _ptr(out), out.numel(), _ptr(status),
+                                      _ptr(num_ok), _stream(stream)), "gq_dequeue_batch")
+
+    def device_view(self) -> _DevView:
+        v = _DevView()
+        _check(lib().gq_device_view(self._h, ctypes.byref(v)), "gq_device_view")
+        return v
+
+    def stats(self, stream=None) -> Stats:
+        s = _Stats()
+        _check(lib().gq_read_stats(self._h, ctypes.byref(s), _stream(stream)), "gq_read_stats")
+        return Stats(*[getattr(s, f[0]) for f in _Stats._fields_])
+
+    def clear_stats(self, stream=None):
+        _check(lib().gq_clear_stats(self._h, _stream(stream)), "gq_clear_stats")
+
+    def check_error(self, stream=None) -> int:
+        return int(lib().gq_check_error(self._h, _stream(stream)))
+
+    # ---- workload drivers --------------------------------------------------
+    def run_mix(self, seed: int, lanes: int, ops_per_lane: int, counts, hist: History = None,
+                stream=None):
+        hc = hist.c() if hist is not None else None
+        _check(lib().gq_run_mix(self._h, seed, lanes, ops_per_lane, _ptr(counts),
+                                ctypes.byref(hc) if hc is not None else None, _stream(stream)),
+               "gq_run_mix")
+
+    def run_balanced(self, lanes: int, rounds: int, counts, hist: History = None, stream=None):
+        hc = hist.c() if hist is not None else None
+        _check(lib().gq_run_balanced(self._h, lanes, rounds, _ptr(counts),
+                                     ctypes.byref(hc) if hc is not None else None,
+                                     _stream(stream)), "gq_run_balanced")
+
+    def run_prodcons(self, seed: int, lanes: int, block: int, lane_role, items_per_producer: int,
+                     target: int, log2_inv_p: int, token_mode: int, counts, hist: History = None,
+                     jitter: int = 0, max_rounds: int = 1 << 26, stream=None):
+        hc = hist.c() if hist is not None else None
+        _check(lib().gq_run_prodcons(self._h, seed, lanes, block, _ptr(lane_role),
+                                     items_per_producer, target, log2_inv_p, token_mode, jitter,
+                                     max_rounds, _ptr(counts),
+                                     ctypes.byref(hc) if hc is not None else None,
+                                     _stream(stream)), "gq_run_prodcons")
+
+    def run_script(self, lanes: int, spread: bool, ops, args, pauses, n_ops, max_ops: int,
+                   hist: History, stream=None):
+        hc = hist.c()
+        _check(lib().gq_run_script(self._h, lanes, 1 if spread else 0, _ptr(ops), _ptr(args),
+                                   _ptr(pauses), _ptr(n_ops), max_ops, ctypes.byref(hc),
+                                   _stream(stream)), "gq_run_script")
+
+
+# ---- probes and device info ---------------------------------------------------
+def probe_faa(ctr, lanes: int, iters: int, per_lane: bool, stream=None):
+    _check(lib().gq_probe_faa(_ptr(ctr), lanes, iters, 1 if per_lane else 0, _stream(stream)),
+           "gq_probe_faa")
+
+
+def probe_cas(slots, nslots: int, stride_bytes: int, lanes: int, iters: int, stream=None):
+    _check(lib().gq_probe_cas(_ptr(slots), nslots, stride_bytes, lanes, iters, _stream(stream)),
+           "gq_probe_cas")
+
+
+def probe_copy(dst, src, n: int, stream=None):
+    _check(lib().gq_probe_copy(_ptr(dst), _ptr(src), n, _stream(stream)), "gq_probe_copy")
+
+
+def probe_fence(lines, lanes: int, iters: int, mode: int, stream=None):
+    _check(lib().gq_probe_fence(_ptr(lines), lanes, iters, mode, _stream(stream)),
+           "gq_probe_fence")
+
+
+def resident_blocks(kernel: str, kind: str, block: int) -> int:
+    out = ctypes.c_uint32(0)
+    _check(lib().gq_resident_blocks(kernel.encode(), KINDS[kind], block, ctypes.byref(out)),
+           "gq_resident_blocks")
+    return int(out.value)
+
+
+def device_info():
+    cus, wave = ctypes.c_uint32(0), ctypes.c_uint32(0)
+    name = ctypes.create_string_buffer(64)
+    _check(lib().gq_device_info(ctypes.byref(cus), ctypes.byref(wave), name, 64), "gq_device_info")
+    return {"cus": int(cus.value), "wave": int(wave.value), "arch": name.value.decode()}

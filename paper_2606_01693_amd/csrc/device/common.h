@@ -1,0 +1,173 @@
+// Device primitives shared by the three queues: scoped atomics, the
+// wave-aggregated fetch-and-add, timestamps and the counter-based random
+// stream used by the benchmark kernels.  gfx950 (CDNA4), 64-lane wavefronts.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../../include/gq.h"
+
+namespace gq {
+
+// ---------------------------------------------------------------------------
+// Agent-scope atomics.  Every shared word is read with an agent-scope atomic
+// load (on gfx950 a plain load may hit a stale line in this XCD's L2), and
+// every update is one 64-bit atomic: the paper's single-word atomicity
+// requirement (Section III-C, Lemma 3) and the absence of CAS2 on GPUs.
+// ---------------------------------------------------------------------------
+#define GQ_AGENT __HIP_MEMORY_SCOPE_AGENT
+
+__device__ __forceinline__ uint64_t ld(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, GQ_AGENT);
+}
+__device__ __forceinline__ int64_t ld(const int64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, GQ_AGENT);
+}
+__device__ __forceinline__ uint32_t ld(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, GQ_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_acq(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, GQ_AGENT);
+}
+__device__ __forceinline__ void st(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, GQ_AGENT);
+}
+__device__ __forceinline__ void st(int64_t* p, int64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, GQ_AGENT);
+}
+__device__ __forceinline__ void st(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, GQ_AGENT);
+}
+__device__ __forceinline__ void st_rel(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, GQ_AGENT);
+}
+// CAS; on failure `expected` receives the current value.
+__device__ __forceinline__ bool cas(uint64_t* p, uint64_t& expected, uint64_t desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
+                                              __ATOMIC_RELAXED, GQ_AGENT);
+}
+__device__ __forceinline__ bool cas_rel(uint64_t* p, uint64_t& expected, uint64_t desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELEASE,
+                                              __ATOMIC_RELAXED, GQ_AGENT);
+}
+__device__ __forceinline__ bool cas_acqrel(uint64_t* p, uint64_t& expected, uint64_t desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_ACQ_REL,
+                                              __ATOMIC_ACQUIRE, GQ_AGENT);
+}
+__device__ __forceinline__ uint64_t faa(uint64_t* p, uint64_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, GQ_AGENT);
+}
+__device__ __forceinline__ int64_t faa(int64_t* p, int64_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, GQ_AGENT);
+}
+__device__ __forceinline__ uint64_t fxor(uint64_t* p, uint64_t v) {
+  return __hip_atomic_fetch_xor(p, v, __ATOMIC_RELAXED, GQ_AGENT);
+}
+__device__ __forceinline__ uint64_t fxor_acq(uint64_t* p, uint64_t v) {
+  return __hip_atomic_fetch_xor(p, v, __ATOMIC_ACQUIRE, GQ_AGENT);
+}
+__device__ __forceinline__ uint64_t f_or(uint64_t* p, uint64_t v) {
+  return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, GQ_AGENT);
+}
+__device__ __forceinline__ uint64_t f_and(uint64_t* p, uint64_t v) {
+  return __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, GQ_AGENT);
+}
+__device__ __forceinline__ void fence_acq() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ void fence_rel() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_acqrel() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent"); }
+
+// ---------------------------------------------------------------------------
+// Wavefront helpers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t active_mask() { return __ballot(1); }
+
+// Number of active lanes below this lane in `mask` (the lane's prefix rank).
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t read_first_lane(uint64_t v) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// WaveFAA (Section III-B, Algorithm 1; Lemma 1).  Every lane that reaches
+// this call together forms the mask; the lowest active lane (the leader)
+// performs one fetch-and-add of popcount(mask) * unit on *ctr; the old value
+// is broadcast and each lane receives base + rank * unit, where rank is its
+// prefix count in the mask.  The returned tickets are distinct and
+// consecutive, in the same total order per-lane FAAs would give.  `unit`
+// lets packed counters (G-WFQ's <Counter, ThrIdx> word) step their counter
+// field; the caller decodes.
+__device__ __forceinline__ uint64_t wave_faa(uint64_t* ctr, uint64_t unit) {
+  const uint64_t mask = active_mask();
+  const uint32_t rank = lane_rank(mask);
+  const uint32_t cnt = (uint32_t)__popcll(mask);
+  uint64_t base = 0;
+  if (rank == 0) base = faa(ctr, (uint64_t)cnt * unit);
+  base = read_first_lane(base);
+  return base + (uint64_t)rank * unit;
+}
+
+// Wave sum of a per-lane value; every lane receives the total.
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// One atomic per wave: add the wave total of v to *dst.
+__device__ __forceinline__ void wave_add(uint64_t* dst, uint64_t v) {
+  const uint64_t mask = active_mask();
+  // Inactive lanes contribute nothing; shuffles read 0 from them by zeroing
+  // before the reduction in fully converged code only, so reduce with a
+  // ballot-driven loop that is correct under any mask.
+  uint64_t total = 0;
+  uint64_t m = mask;
+  while (m) {
+    const int l = __ffsll((unsigned long long)m) - 1;
+    total += __shfl(v, l, 64);
+    m &= m - 1;
+  }
+  if (lane_rank(mask) == 0 && total) faa(dst, total);
+}
+
+// ---------------------------------------------------------------------------
+// Device timestamp: the constant-rate (100 MHz) real-time counter, read with
+// the wait that makes the value available before any later memory access.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t stamp() {
+  uint64_t t;
+  asm volatile("s_memrealtime %0\n\ts_waitcnt lgkmcnt(0)" : "=s"(t)::"memory");
+  return t;
+}
+
+// Short pause (used by seeded jitter in tests and by bounded back-off).
+__device__ __forceinline__ void pause(uint32_t units) {
+  for (uint32_t i = 0; i < units; i++) __builtin_amdgcn_s_sleep(1);
+}
+
+// ---------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): the c-th output of the
+// generator seeded with `seed` is the finalizer applied to
+// seed + (c + 1) * 0x9E3779B97F4A7C15.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t c) {
+  uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Device error latch: first error wins.
+__device__ __forceinline__ void latch_error(uint64_t* err, uint64_t code) {
+  uint64_t zero = 0;
+  cas(err, zero, code);
+}
+
+// Statistics slots (gq_stats order).
+enum StatSlot { S_OK_ENQ = 0, S_OK_DEQ, S_FULL, S_EMPTY, S_CAS_FAIL, S_TICKETS, S_SLOW, S_HELPS, S_NUM };
+
+}  // namespace gq

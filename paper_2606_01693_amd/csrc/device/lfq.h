@@ -1,0 +1,221 @@
+// G-LFQ: the bounded lock-free queue of Section III-B (Algorithm 1).
+//
+// Structure (Section III-B, "Data structure"): an inner ring of 2n physical
+// slots holding packed 64-bit entries, monotone Head/Tail ticket counters and
+// a signed Threshold for empty detection; an outer queue built from two such
+// rings -- `aq` (allocated indices) and `fq` (free indices) -- plus an array
+// of n payload cells, so the rings move 32-bit indices, not payloads.
+//
+// Entry word (64 bits): Index in bits [0,32), Safe in bit 32, Cycle in bits
+// [33,64) -- a 31-bit cycle tag compared modulo 2^31 (Lemma 2).  Index is a
+// payload index, BOT (empty) or BOTC (consumed).
+//
+// Tickets: slot(t) = t mod 2n, cycle(t) = floor(t / 2n) mod 2^31, reserved
+// with the wave-aggregated fetch-and-add (Lemma 1).
+#pragma once
+#include "common.h"
+
+namespace gq {
+namespace lfq {
+
+constexpr uint32_t BOT = 0xFFFFFFFFu;   // empty slot
+constexpr uint32_t BOTC = 0xFFFFFFFEu;  // consumed slot
+constexpr uint32_t CYC_BITS = 31;
+constexpr uint32_t CYC_MASK = (1u << CYC_BITS) - 1u;
+constexpr uint32_t CYC_HALF = 1u << (CYC_BITS - 1);
+// Fail-safe bound on retries of one inner operation.  Reaching it means an
+// invariant broke (the algorithm retries only while other lanes progress);
+// the operation then latches GQ_ERR_DEVICE and gives up instead of spinning.
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+
+__device__ __forceinline__ uint32_t e_idx(uint64_t e) { return (uint32_t)e; }
+__device__ __forceinline__ bool e_safe(uint64_t e) { return (e >> 32) & 1u; }
+__device__ __forceinline__ uint32_t e_cyc(uint64_t e) { return (uint32_t)(e >> 33); }
+__device__ __forceinline__ uint64_t e_make(uint32_t cyc, bool safe, uint32_t idx) {
+  return ((uint64_t)(cyc & CYC_MASK) << 33) | ((uint64_t)safe << 32) | idx;
+}
+__device__ __forceinline__ bool idx_free(uint32_t i) { return i >= BOTC; }  // BOT or BOTC
+
+// a is strictly older than b: 0 < (b - a) mod R < R/2  (Lemma 2 / Lemma 4).
+__device__ __forceinline__ bool older(uint32_t a, uint32_t b) {
+  const uint32_t d = (b - a) & CYC_MASK;
+  return d != 0 && d < CYC_HALF;
+}
+
+// Geometry of one ring, derived from the queue view.
+struct Ring {
+  uint64_t* slots;
+  uint64_t* head;
+  uint64_t* tail;
+  int64_t* thr;
+  uint32_t log2_2n;   // log2(2n)
+  uint32_t log2_L;    // entries per line (remap mode)
+  uint32_t padded;    // 1: one entry per 128-byte line
+  int64_t thr_reset;  // 3n - 1
+
+  __device__ __forceinline__ uint64_t* at(uint64_t j) const {
+    if (padded) return slots + (j << 4);  // 128-byte stride
+    // remap: consecutive tickets land on different 128-byte lines
+    const uint32_t log2_M = log2_2n - log2_L;
+    const uint64_t pos = ((j & ((1ull << log2_M) - 1)) << log2_L) | (j >> log2_M);
+    return slots + pos;
+  }
+  __device__ __forceinline__ uint64_t slot_of(uint64_t t) const {
+    return t & ((1ull << log2_2n) - 1);
+  }
+  __device__ __forceinline__ uint32_t cycle_of(uint64_t t) const {
+    return (uint32_t)(t >> log2_2n) & CYC_MASK;
+  }
+};
+
+// Threshold reset value.  Algorithm 1 resets Threshold to 3n - 1, which is
+// 2n (the most tickets that can separate Head from a newly installed entry)
+// plus n - 1 concurrent dequeuers that may still fail after the reset; that
+// accounting assumes at most n lanes use the queue (the configuration of
+// Lemma 4, k <= n).  With k lanes the same accounting gives 2n + k - 1, so
+// the value used is 2n + max(n, k) - 1, equal to 3n - 1 whenever k <= n.
+__host__ __device__ __forceinline__ int64_t threshold_reset(const gq_dev& q) {
+  const int64_t n = (int64_t)q.capacity;
+  const int64_t k = (int64_t)q.max_threads;
+  return 2 * n + (k > n ? k : n) - 1;
+}
+
+__device__ __forceinline__ Ring make_ring(const gq_ring_view& v, const gq_dev& q) {
+  Ring r;
+  r.slots = v.slots;
+  r.head = v.head;
+  r.tail = v.tail;
+  r.thr = v.threshold;
+  r.log2_2n = q.log2_cap + 1;
+  r.log2_L = r.log2_2n < 4 ? r.log2_2n : 4;
+  r.padded = q.slot_mode == GQ_SLOTS_PADDED;
+  r.thr_reset = threshold_reset(q);
+  return r;
+}
+
+// Move Tail forward to at least h (sCQ catch-up, Algorithm 1 "catch up Tail").
+__device__ __forceinline__ void catchup(const Ring& r, uint64_t t, uint64_t h) {
+  while (!cas(r.tail, t, h)) {
+    h = ld(r.head);
+    t = ld(r.tail);
+    if (t >= h) break;
+  }
+}
+
+// Inner enqueue of index `idx` (Algorithm 1, TryEnq, retried until success).
+// The install CAS is a release so that the payload written before it is
+// visible to whoever consumes the entry.  An index ring never holds more than
+// n indices in 2n slots, so the retry loop ends (lock-freedom, Section III-B).
+template <bool RELEASE>
+__device__ __forceinline__ bool ring_enq(const Ring& r, uint32_t idx, uint32_t& cas_fail,
+                                         uint64_t* err) {
+  bool done = false;
+  for (uint32_t spin = 0; !done; spin++) {
+    if (spin >= SPIN_LIMIT) {
+      latch_error(err, (uint64_t)(-GQ_ERR_DEVICE));
+      return false;
+    }
+    const uint64_t t = wave_faa(r.tail, 1);
+    const uint32_t c = r.cycle_of(t);
+    uint64_t* p = r.at(r.slot_of(t));
+    uint64_t e = ld(p);
+    while (true) {
+      if (older(e_cyc(e), c) && (e_safe(e) || ld(r.head) <= t) && idx_free(e_idx(e))) {
+        const uint64_t ne = e_make(c, true, idx);
+        const bool ok = RELEASE ? cas_rel(p, e, ne) : cas(p, e, ne);
+        if (ok) {
+          if (ld(r.thr) != r.thr_reset) st(r.thr, r.thr_reset);
+          done = true;
+          break;
+        }
+        cas_fail++;
+        continue;  // re-test the entry the CAS returned, same ticket
+      }
+      break;  // this ticket is unusable: take a new one
+    }
+  }
+  return true;
+}
+
+// Inner dequeue (Algorithm 1, TryDeq, retried until an index or EMPTY).
+// Returns the index, or BOT for EMPTY.  Consume is an atomic XOR that turns
+// the index field into BOTC and leaves Cycle/Safe alone; between install and
+// consume only Safe can change, so the XOR is exact.
+template <bool ACQUIRE>
+__device__ __forceinline__ uint32_t ring_deq(const Ring& r, uint32_t& cas_fail, uint64_t* err) {
+  for (uint32_t spin = 0;; spin++) {
+    if (spin >= SPIN_LIMIT) {
+      latch_error(err, (uint64_t)(-GQ_ERR_DEVICE));
+      return BOT;
+    }
+    if (ld(r.thr) < 0) return BOT;
+    const uint64_t h = wave_faa(r.head, 1);
+    const uint32_t c = r.cycle_of(h);
+    uint64_t* p = r.at(r.slot_of(h));
+    uint64_t e = ld(p);
+    while (true) {
+      if (e_cyc(e) == c && !idx_free(e_idx(e))) {
+        const uint64_t x = (uint64_t)(e_idx(e) ^ BOTC);
+        if (ACQUIRE) fxor_acq(p, x); else fxor(p, x);
+        return e_idx(e);
+      }
+      if (older(e_cyc(e), c)) {
+        // the slot is stale for ticket h: mark it empty at cycle c, or, when
+        // it still holds an older live index, clear Safe so no enqueuer with
+        // an earlier ticket than Head installs behind it
+        const uint64_t ne = idx_free(e_idx(e)) ? e_make(c, e_safe(e), BOT)
+                                               : e_make(e_cyc(e), false, e_idx(e));
+        if (!cas(p, e, ne)) {
+          cas_fail++;
+          continue;  // re-examine the returned entry
+        }
+      }
+      break;
+    }
+    const uint64_t t = ld(r.tail);
+    if (t <= h + 1) {
+      catchup(r, t, h + 1);
+      faa(r.thr, (int64_t)-1);
+      return BOT;
+    }
+    if (faa(r.thr, (int64_t)-1) <= 0) return BOT;
+  }
+}
+
+// ---- outer queue (Section III-B: indices move through aq/fq) -------------
+// enqueue: idx <- fq.deq (EMPTY means FULL); data[idx] <- x; aq.enq(idx).
+// dequeue: idx <- aq.deq (EMPTY means EMPTY); x <- data[idx]; fq.enq(idx).
+__device__ __forceinline__ int enqueue(const gq_dev& q, uint64_t item, uint32_t& cas_fail) {
+  const Ring fq = make_ring(q.fq, q);
+  const Ring aq = make_ring(q.aq, q);
+  // The payload store below depends on idx, and the previous holder of idx
+  // finished reading the cell before releasing idx into fq: no acquire needed.
+  const uint32_t idx = ring_deq<false>(fq, cas_fail, q.err);
+  if (idx == BOT) return GQ_FULL;
+  if (idx >= q.capacity) {  // never taken: guards the payload array
+    latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
+    return GQ_FULL;
+  }
+  if (q.item_width == 8) ((uint64_t*)q.data)[idx] = item;
+  else ((uint32_t*)q.data)[idx] = (uint32_t)item;
+  ring_enq<true>(aq, idx, cas_fail, q.err);  // release publishes the payload
+  return GQ_OK;
+}
+
+__device__ __forceinline__ int dequeue(const gq_dev& q, uint64_t* item, uint32_t& cas_fail) {
+  const Ring aq = make_ring(q.aq, q);
+  const Ring fq = make_ring(q.fq, q);
+  const uint32_t idx = ring_deq<true>(aq, cas_fail, q.err);  // acquire pairs with the install
+  if (idx == BOT) return GQ_EMPTY;
+  if (idx >= q.capacity) {  // never taken: guards the payload array
+    latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
+    return GQ_EMPTY;
+  }
+  *item = q.item_width == 8 ? ((const uint64_t*)q.data)[idx]
+                            : (uint64_t)((const uint32_t*)q.data)[idx];
+  ring_enq<true>(fq, idx, cas_fail, q.err);  // release: the read above completes first
+  return GQ_OK;
+}
+
+}  // namespace lfq
+}  // namespace gq

@@ -1,0 +1,772 @@
+// libgq.so: host side of the C ABI (include/gq.h, include/gq_bench.h) and the
+// kernels it launches.  One process, one GPU, HIP streams passed in by the
+// caller; every device word the queues share lives in one allocation.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/gq.h"
+#include "../../include/gq_bench.h"
+#include "../../include/gq_device.h"
+
+using namespace gq;
+
+// A failed HIP call returns GQ_ERR_HIP; with GQ_VERBOSE set in the
+// environment the HIP error is also printed to stderr.
+static gq_status hip_fail(hipError_t e, const char* what, int line) {
+  if (getenv("GQ_VERBOSE"))
+    fprintf(stderr, "libgq: %s failed at line %d: %s\n", what, line, hipGetErrorString(e));
+  return GQ_ERR_HIP;
+}
+#define HIP_OK(expr)                                           \
+  do {                                                         \
+    hipError_t e_ = (expr);                                    \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr, __LINE__); \
+  } while (0)
+// Kernel launches report through hipGetLastError, which also returns errors
+// left behind by earlier, unrelated runtime calls (e.g. a not-ready stream
+// query); clear it before every launch so only the launch is judged.
+#define LAUNCH(...)              \
+  do {                           \
+    (void)hipGetLastError();     \
+    hipLaunchKernelGGL(__VA_ARGS__); \
+  } while (0)
+
+namespace {
+
+constexpr uint32_t kBlock = 256;
+constexpr uint64_t kCtrlBytes = 8192;
+constexpr uint64_t kLine = 256;  // counters live on separate 256-byte lines
+
+// Control block layout (byte offsets).
+enum : uint64_t {
+  OFF_AQ_HEAD = 0 * kLine,
+  OFF_AQ_TAIL = 1 * kLine,
+  OFF_AQ_THR = 2 * kLine,
+  OFF_FQ_HEAD = 3 * kLine,
+  OFF_FQ_TAIL = 4 * kLine,
+  OFF_FQ_THR = 5 * kLine,
+  OFF_ERR = 6 * kLine,
+  OFF_STATS = 7 * kLine,   // 8 words
+  OFF_YMC_T = 8 * kLine,
+  OFF_YMC_H = 9 * kLine,
+  OFF_TAKEN = 10 * kLine,  // producer/consumer driver: items taken so far
+};
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+inline bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+inline uint32_t ilog2(uint64_t x) {
+  uint32_t l = 0;
+  while ((1ull << l) < x) l++;
+  return l;
+}
+
+struct Layout {
+  uint64_t slots_aq, slots_fq, data, rec_aq, rec_fq, ymc_pool, ymc_handles, total;
+};
+
+bool kind_supported(gq_kind kind) { return kind == GQ_LFQ; }
+
+gq_status plan(gq_kind kind, uint64_t n, uint32_t w, uint32_t k, const gq_options* o,
+               Layout* L) {
+  if (!kind_supported(kind)) return GQ_ERR_INVALID;
+  if (!is_pow2(n) || n < 2 || n > (1ull << 30)) return GQ_ERR_INVALID;
+  if (w != 4 && w != 8) return GQ_ERR_INVALID;
+  if (k == 0 || k > (1u << 24)) return GQ_ERR_INVALID;
+  if (o && (o->flags != 0 || o->slot_mode > GQ_SLOTS_PADDED)) return GQ_ERR_INVALID;
+  const uint32_t mode = o ? o->slot_mode : GQ_SLOTS_REMAP;
+  const uint64_t slot_bytes = 2 * n * (mode == GQ_SLOTS_PADDED ? 128 : 8);
+  uint64_t off = kCtrlBytes;
+  L->slots_aq = off;
+  off = align_up(off + slot_bytes, 4096);
+  L->slots_fq = off;
+  off = align_up(off + slot_bytes, 4096);
+  L->data = off;
+  off = align_up(off + n * w, 4096);
+  L->rec_aq = L->rec_fq = L->ymc_pool = L->ymc_handles = 0;
+  L->total = off;
+  return GQ_OK;
+}
+
+// ---- initialisation --------------------------------------------------------
+// Empty ring: every entry all ones (cycle = -1 mod 2^31, Safe = 1, BOT), Head
+// = Tail = 0, Threshold = -1.  Full free ring: tickets 0..n-1 already
+// enqueued in cycle 0 -- slots [0, n) hold <0, 1, i>, slots [n, 2n) empty --
+// Head = 0, Tail = n, Threshold = its reset value (3n - 1 when k <= n).
+__global__ void k_init_lfq(gq_dev q) {
+  const uint64_t two_n = 2 * q.capacity;
+  const lfq::Ring aq = lfq::make_ring(q.aq, q);
+  const lfq::Ring fq = lfq::make_ring(q.fq, q);
+  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < two_n;
+       j += (uint64_t)gridDim.x * blockDim.x) {
+    st(aq.at(j), ~0ull);
+    st(fq.at(j), j < q.capacity ? lfq::e_make(0, true, (uint32_t)j) : ~0ull);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st(q.aq.head, 0ull);
+    st(q.aq.tail, 0ull);
+    st(q.aq.threshold, (int64_t)-1);
+    st(q.fq.head, 0ull);
+    st(q.fq.tail, q.capacity);
+    st(q.fq.threshold, lfq::threshold_reset(q));
+    st(q.err, 0ull);
+    for (int s = 0; s < S_NUM; s++) st(q.stats + s, 0ull);
+  }
+}
+
+uint32_t grid_for(uint64_t work, uint32_t block, uint32_t cap) {
+  uint64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (uint32_t)g;
+}
+
+// ---- batched operations ----------------------------------------------------
+template <int KIND>
+__global__ void k_enqueue_batch(gq_dev q, const void* items, uint64_t m, uint8_t* status,
+                                uint64_t* nok) {
+  const uint64_t gtid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t launched = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t stride = launched < q.max_threads ? launched : q.max_threads;
+  uint64_t ok = 0;
+  uint32_t cf = 0;
+  for (uint64_t i = gtid; gtid < stride && i < m; i += stride) {
+    const uint64_t item = q.item_width == 8 ? ((const uint64_t*)items)[i]
+                                            : (uint64_t)((const uint32_t*)items)[i];
+    const int s = gq_enqueue_k<KIND>(q, item, (uint32_t)gtid, cf);
+    if (status) status[i] = (uint8_t)s;
+    ok += s == GQ_OK;
+  }
+  wave_add(q.stats + S_OK_ENQ, ok);
+  wave_add(q.stats + S_CAS_FAIL, cf);
+  if (nok) wave_add(nok, ok);
+}
+
+template <int KIND>
+__global__ void k_dequeue_batch(gq_dev q, void* out, uint64_t m, uint8_t* status, uint64_t* nok) {
+  const uint64_t gtid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t launched = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t stride = launched < q.max_threads ? launched : q.max_threads;
+  uint64_t ok = 0;
+  uint32_t cf = 0;
+  for (uint64_t i = gtid; gtid < stride && i < m; i += stride) {
+    uint64_t v = 0;
+    const int s = gq_dequeue_k<KIND>(q, &v, (uint32_t)gtid, cf);
+    if (s != GQ_OK) v = 0;
+    if (q.item_width == 8) ((uint64_t*)out)[i] = v;
+    else ((uint32_t*)out)[i] = (uint32_t)v;
+    if (status) status[i] = (uint8_t)s;
+    ok += s == GQ_OK;
+  }
+  wave_add(q.stats + S_OK_DEQ, ok);
+  wave_add(q.stats + S_CAS_FAIL, cf);
+  if (nok) wave_add(nok, ok);
+}
+
+// ---- history recording -----------------------------------------------------
+struct Rec {
+  gq_history h;
+  bool on;
+  __device__ __forceinline__ void put(uint64_t g, uint32_t r, int op, int s, uint64_t val,
+                                      uint64_t t0, uint64_t t1) const {
+    if (!on || r >= h.per_lane) return;
+    const uint64_t i = g * h.per_lane + r;
+    h.val[i] = val;
+    h.call[i] = t0;
+    h.ret[i] = t1;
+    h.opst[i] = (uint8_t)(op | (s << 1));
+  }
+};
+
+// The end stamp is taken after an agent-scope release fence, so every write
+// of the operation is complete and visible before its recorded return.
+__device__ __forceinline__ uint64_t end_stamp() {
+  fence_rel();
+  return stamp();
+}
+
+// ---- mixed workload --------------------------------------------------------
+template <int KIND, bool REC>
+__global__ __launch_bounds__(256) void k_mix(gq_dev q, uint64_t seed, uint32_t ops,
+                                             uint64_t* counts, Rec rec) {
+  const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  uint64_t seq = 0, ok_e = 0, ok_d = 0, full = 0, empty = 0;
+  uint32_t cf = 0;
+  for (uint32_t r = 0; r < ops; r++) {
+    const bool is_enq = (splitmix64(seed, (g << 32) | r) >> 63) == 0;
+    const uint64_t t0 = REC ? stamp() : 0;
+    uint64_t v;
+    int s;
+    if (is_enq) {
+      v = (g << 32) | (seq + 1);
+      s = gq_enqueue_k<KIND>(q, v, (uint32_t)g, cf);
+      if (s == GQ_OK) { seq++; ok_e++; } else full++;
+    } else {
+      v = 0;
+      s = gq_dequeue_k<KIND>(q, &v, (uint32_t)g, cf);
+      if (s == GQ_OK) ok_d++; else { empty++; v = 0; }
+    }
+    if (REC) rec.put(g, r, is_enq ? 0 : 1, s, v, t0, end_stamp());
+  }
+  if (REC && rec.h.count) rec.h.count[g] = ops;
+  wave_add(counts + 0, ok_e);
+  wave_add(counts + 1, ok_d);
+  wave_add(counts + 2, full);
+  wave_add(counts + 3, empty);
+  wave_add(q.stats + S_CAS_FAIL, cf);
+}
+
+// ---- balanced workload -----------------------------------------------------
+template <int KIND, bool REC>
+__global__ __launch_bounds__(256) void k_balanced(gq_dev q, uint32_t rounds, uint64_t* counts,
+                                                  Rec rec) {
+  const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  uint64_t seq = 0, ok_e = 0, ok_d = 0, full = 0, empty = 0;
+  uint32_t cf = 0, r = 0;
+  for (uint32_t k = 0; k < rounds; k++) {
+    uint64_t t0 = REC ? stamp() : 0;
+    uint64_t v = (g << 32) | (seq + 1);
+    int s = gq_enqueue_k<KIND>(q, v, (uint32_t)g, cf);
+    if (s == GQ_OK) { seq++; ok_e++; } else full++;
+    if (REC) rec.put(g, r, 0, s, v, t0, end_stamp());
+    r++;
+    t0 = REC ? stamp() : 0;
+    v = 0;
+    s = gq_dequeue_k<KIND>(q, &v, (uint32_t)g, cf);
+    if (s == GQ_OK) ok_d++; else { empty++; v = 0; }
+    if (REC) rec.put(g, r, 1, s, v, t0, end_stamp());
+    r++;
+  }
+  if (REC && rec.h.count) rec.h.count[g] = r;
+  wave_add(counts + 0, ok_e);
+  wave_add(counts + 1, ok_d);
+  wave_add(counts + 2, full);
+  wave_add(counts + 3, empty);
+  wave_add(q.stats + S_CAS_FAIL, cf);
+}
+
+// ---- producer / consumer workload -----------------------------------------
+template <int KIND, bool REC>
+__global__ void k_prodcons(gq_dev q, uint64_t seed, const uint8_t* role, uint32_t quota,
+                           uint64_t target, uint32_t log2_inv_p, uint32_t token_mode,
+                           uint32_t jitter, uint64_t max_rounds, uint64_t* taken,
+                           uint64_t* counts, Rec rec) {
+  const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const bool producer = role[g] == 0;
+  uint64_t seq = 0, ok_e = 0, ok_d = 0, full = 0, empty = 0;
+  uint32_t cf = 0, r = 0;
+  for (uint64_t k = 0;; k++) {
+    if (producer ? seq >= quota : ld(taken) >= target) break;
+    if (k >= max_rounds) {
+      latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
+      break;
+    }
+    const uint64_t draw = splitmix64(seed, (g << 32) | (k & 0xFFFFFFFFull));
+    if (jitter) pause((uint32_t)(draw & 0xFFFF) % (jitter + 1));
+    const bool active = log2_inv_p == 0 || (draw >> (64 - log2_inv_p)) == 0;
+    if (!active) continue;
+    const uint64_t t0 = REC ? stamp() : 0;
+    if (producer) {
+      const uint64_t v = token_mode == 0 ? ((g << 32) | (seq + 1)) : ((g << 20) | seq);
+      const int s = gq_enqueue_k<KIND>(q, v, (uint32_t)g, cf);
+      if (s == GQ_OK) { seq++; ok_e++; } else full++;
+      if (REC) rec.put(g, r, 0, s, v, t0, end_stamp());
+    } else {
+      uint64_t v = 0;
+      const int s = gq_dequeue_k<KIND>(q, &v, (uint32_t)g, cf);
+      if (s == GQ_OK) { ok_d++; faa(taken, 1ull); } else { empty++; v = 0; }
+      if (REC) rec.put(g, r, 1, s, v, t0, end_stamp());
+    }
+    r++;
+  }
+  if (REC && rec.h.count) rec.h.count[g] = r;
+  wave_add(counts + 0, ok_e);
+  wave_add(counts + 1, ok_d);
+  wave_add(counts + 2, full);
+  wave_add(counts + 3, empty);
+  wave_add(q.stats + S_CAS_FAIL, cf);
+}
+
+// ---- scripted small runs ---------------------------------------------------
+template <int KIND>
+__global__ void k_script(gq_dev q, uint32_t lanes, uint32_t spread, const uint8_t* ops,
+                         const uint64_t* args, const uint16_t* pauses, const uint32_t* n_ops,
+                         uint32_t max_ops, Rec rec) {
+  uint32_t g;
+  if (spread) {
+    if (threadIdx.x != 0) return;  // one active lane per wavefront
+    g = blockIdx.x;
+  } else {
+    g = threadIdx.x;
+  }
+  if (g >= lanes) return;
+  uint32_t cf = 0;
+  for (uint32_t r = 0; r < n_ops[g]; r++) {
+    const uint64_t i = (uint64_t)g * max_ops + r;
+    pause(pauses[i]);
+    const uint64_t t0 = stamp();
+    uint64_t v = args[i];
+    int s;
+    if (ops[i] == 0) {
+      s = gq_enqueue_k<KIND>(q, v, g, cf);
+    } else {
+      v = 0;
+      s = gq_dequeue_k<KIND>(q, &v, g, cf);
+      if (s != GQ_OK) v = 0;
+    }
+    rec.put(g, r, ops[i], s, v, t0, end_stamp());
+  }
+  if (rec.h.count) rec.h.count[g] = n_ops[g];
+}
+
+// ---- roofline probes ---------------------------------------------------------
+__global__ void k_probe_faa(uint64_t* ctr, uint32_t iters, uint32_t per_lane, uint64_t* sink) {
+  uint64_t acc = 0;
+  for (uint32_t i = 0; i < iters; i++) {
+    if (per_lane) acc += faa(ctr, 1ull);
+    else acc += wave_faa(ctr, 1ull);
+  }
+  if (acc == 0x5555555555555555ull) sink[0] = acc;
+}
+
+__global__ void k_probe_cas(uint64_t* slots, uint64_t nslots, uint32_t stride_words,
+                            uint32_t iters, uint64_t* sink) {
+  const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t nl = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t acc = 0;
+  for (uint32_t i = 0; i < iters; i++) {
+    const uint64_t t = (g + i * nl) % nslots;
+    uint64_t* p = slots + t * stride_words;
+    uint64_t e = ld(p);
+    if (!cas(p, e, e + 1)) acc++;
+  }
+  if (acc == 0x5555555555555555ull) sink[0] = acc;
+}
+
+__global__ void k_probe_copy(uint64_t* dst, const uint64_t* src, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 2;
+  for (uint64_t i = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) * 2; i < n; i += stride) {
+    if (i + 1 < n) {
+      const ulonglong2 v = *(const ulonglong2*)(src + i);
+      *(ulonglong2*)(dst + i) = v;
+    } else {
+      dst[i] = src[i];
+    }
+  }
+}
+
+__global__ void k_probe_fence(uint64_t* lines, uint32_t iters, uint32_t mode) {
+  const uint64_t w = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / 64;
+  uint64_t* p = lines + w * 32;  // one 256-byte line per wavefront
+  for (uint32_t i = 0; i < iters; i++) {
+    if (mode & 1) fence_rel();
+    if ((threadIdx.x & 63) == 0) st(p, (uint64_t)i);
+    if (mode & 2) fence_acq();
+  }
+}
+
+__global__ void k_sink() {}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+struct gq_queue {
+  gq_kind kind;
+  uint64_t n;
+  uint32_t w, k;
+  gq_options opt;
+  char* buf;
+  uint64_t bytes;
+  bool owns;
+  gq_dev dev;
+  Layout L;
+};
+
+static hipStream_t S(void* s) { return (hipStream_t)s; }
+
+static gq_status launch_init(gq_queue* q, hipStream_t s) {
+  const uint64_t slots = 2 * q->n;
+  const uint32_t grid = grid_for(slots, kBlock, 4096);
+  switch (q->kind) {
+    case GQ_LFQ:
+      LAUNCH(k_init_lfq, dim3(grid), dim3(kBlock), 0, s, q->dev);
+      break;
+    default:
+      return GQ_ERR_INVALID;
+  }
+  HIP_OK(hipGetLastError());
+  return GQ_OK;
+}
+
+// Batches run on at most max_threads lanes (grid-stride over the items): the
+// queues' empty detection and G-WFQ's records are sized for that many lanes.
+static uint32_t batch_grid(const gq_queue* q, uint64_t m) {
+  uint32_t cap = (q->k + kBlock - 1) / kBlock;
+  if (cap < 1) cap = 1;
+  if (cap > 8192) cap = 8192;
+  return grid_for(m, kBlock, cap);
+}
+
+template <int KIND>
+static void launch_enq(gq_queue* q, const void* items, uint64_t m, uint8_t* st, uint64_t* nok,
+                       hipStream_t s) {
+  const uint32_t grid = batch_grid(q, m);
+  LAUNCH(k_enqueue_batch<KIND>, dim3(grid), dim3(kBlock), 0, s, q->dev, items, m, st,
+                     nok);
+}
+template <int KIND>
+static void launch_deq(gq_queue* q, void* out, uint64_t m, uint8_t* st, uint64_t* nok,
+                       hipStream_t s) {
+  const uint32_t grid = batch_grid(q, m);
+  LAUNCH(k_dequeue_batch<KIND>, dim3(grid), dim3(kBlock), 0, s, q->dev, out, m, st,
+                     nok);
+}
+
+extern "C" {
+
+const char* gq_status_str(gq_status s) {
+  switch (s) {
+    case GQ_OK: return "ok";
+    case GQ_EMPTY: return "empty";
+    case GQ_FULL: return "full";
+    case GQ_ERR_INVALID: return "invalid argument";
+    case GQ_ERR_NOMEM: return "out of device memory or buffer too small";
+    case GQ_ERR_HIP: return "HIP runtime error";
+    case GQ_ERR_RESIDENCY: return "lanes cannot all be co-resident";
+    case GQ_ERR_CYCLE_BOUND: return "cycle-tag bound R > D*k/n + 6 violated";
+    case GQ_ERR_POOL_EXHAUSTED: return "G-WFQ-YMC cell pool exhausted";
+    case GQ_ERR_DEVICE: return "device-side invariant or bound violated";
+  }
+  return "unknown status";
+}
+
+gq_status gq_required_bytes(gq_kind kind, uint64_t capacity, uint32_t item_width,
+                            uint32_t max_threads, const gq_options* opts, uint64_t* bytes) {
+  if (!bytes) return GQ_ERR_INVALID;
+  Layout L;
+  gq_status st = plan(kind, capacity, item_width, max_threads, opts, &L);
+  if (st != GQ_OK) return st;
+  *bytes = L.total;
+  return GQ_OK;
+}
+
+gq_status gq_create(gq_kind kind, uint64_t capacity, uint32_t item_width, uint32_t max_threads,
+                    const gq_options* opts, void* dev_buf, uint64_t buf_bytes, gq_queue** out) {
+  if (!out) return GQ_ERR_INVALID;
+  *out = nullptr;
+  Layout L;
+  gq_status st = plan(kind, capacity, item_width, max_threads, opts, &L);
+  if (st != GQ_OK) return st;
+  gq_queue* q = new (std::nothrow) gq_queue();
+  if (!q) return GQ_ERR_NOMEM;
+  q->kind = kind;
+  q->n = capacity;
+  q->w = item_width;
+  q->k = max_threads;
+  memset(&q->opt, 0, sizeof(q->opt));
+  if (opts) q->opt = *opts;
+  q->L = L;
+  if (dev_buf) {
+    if (buf_bytes < L.total || ((uintptr_t)dev_buf & 255)) {
+      delete q;
+      return GQ_ERR_NOMEM;
+    }
+    q->buf = (char*)dev_buf;
+    q->bytes = buf_bytes;
+    q->owns = false;
+  } else {
+    void* p = nullptr;
+    if (hipMalloc(&p, L.total) != hipSuccess) {
+      delete q;
+      return GQ_ERR_NOMEM;
+    }
+    q->buf = (char*)p;
+    q->bytes = L.total;
+    q->owns = true;
+  }
+  gq_dev& d = q->dev;
+  memset(&d, 0, sizeof(d));
+  d.kind = kind;
+  d.item_width = item_width;
+  d.log2_cap = ilog2(capacity);
+  d.slot_mode = q->opt.slot_mode;
+  d.max_threads = max_threads;
+  d.capacity = capacity;
+  d.data = q->buf + L.data;
+  d.aq.slots = (uint64_t*)(q->buf + L.slots_aq);
+  d.aq.head = (uint64_t*)(q->buf + OFF_AQ_HEAD);
+  d.aq.tail = (uint64_t*)(q->buf + OFF_AQ_TAIL);
+  d.aq.threshold = (int64_t*)(q->buf + OFF_AQ_THR);
+  d.fq.slots = (uint64_t*)(q->buf + L.slots_fq);
+  d.fq.head = (uint64_t*)(q->buf + OFF_FQ_HEAD);
+  d.fq.tail = (uint64_t*)(q->buf + OFF_FQ_TAIL);
+  d.fq.threshold = (int64_t*)(q->buf + OFF_FQ_THR);
+  d.err = (uint64_t*)(q->buf + OFF_ERR);
+  d.stats = (uint64_t*)(q->buf + OFF_STATS);
+  d.ymc_ctr = (uint64_t*)(q->buf + OFF_YMC_T);
+  st = launch_init(q, nullptr);
+  if (st == GQ_OK) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) st = hip_fail(e, "hipDeviceSynchronize", __LINE__);
+  }
+  if (st != GQ_OK) {
+    if (q->owns) (void)hipFree(q->buf);
+    delete q;
+    return st;
+  }
+  *out = q;
+  return GQ_OK;
+}
+
+gq_status gq_destroy(gq_queue* q) {
+  if (!q) return GQ_ERR_INVALID;
+  if (q->owns && q->buf) (void)hipFree(q->buf);
+  delete q;
+  return GQ_OK;
+}
+
+gq_status gq_reset(gq_queue* q, void* stream) {
+  if (!q) return GQ_ERR_INVALID;
+  return launch_init(q, S(stream));
+}
+
+gq_status gq_enqueue_batch(gq_queue* q, const void* d_items, uint64_t m, uint8_t* d_status,
+                           uint64_t* d_num_ok, void* stream) {
+  if (!q || (!d_items && m)) return GQ_ERR_INVALID;
+  if (m == 0) return GQ_OK;
+  switch (q->kind) {
+    case GQ_LFQ: launch_enq<GQ_LFQ>(q, d_items, m, d_status, d_num_ok, S(stream)); break;
+    default: return GQ_ERR_INVALID;
+  }
+  HIP_OK(hipGetLastError());
+  return GQ_OK;
+}
+
+gq_status gq_dequeue_batch(gq_queue* q, void* d_out, uint64_t m, uint8_t* d_status,
+                           uint64_t* d_num_ok, void* stream) {
+  if (!q || (!d_out && m)) return GQ_ERR_INVALID;
+  if (m == 0) return GQ_OK;
+  switch (q->kind) {
+    case GQ_LFQ: launch_deq<GQ_LFQ>(q, d_out, m, d_status, d_num_ok, S(stream)); break;
+    default: return GQ_ERR_INVALID;
+  }
+  HIP_OK(hipGetLastError());
+  return GQ_OK;
+}
+
+gq_status gq_device_view(const gq_queue* q, gq_dev* out) {
+  if (!q || !out) return GQ_ERR_INVALID;
+  *out = q->dev;
+  return GQ_OK;
+}
+
+gq_status gq_read_stats(gq_queue* q, gq_stats* out, void* stream) {
+  if (!q || !out) return GQ_ERR_INVALID;
+  uint64_t s[S_NUM];
+  HIP_OK(hipMemcpyAsync(s, q->dev.stats, sizeof(s), hipMemcpyDeviceToHost, S(stream)));
+  HIP_OK(hipStreamSynchronize(S(stream)));
+  out->ok_enq = s[S_OK_ENQ];
+  out->ok_deq = s[S_OK_DEQ];
+  out->full = s[S_FULL];
+  out->empty = s[S_EMPTY];
+  out->cas_fail = s[S_CAS_FAIL];
+  out->tickets = s[S_TICKETS];
+  out->slow_enter = s[S_SLOW];
+  out->helps = s[S_HELPS];
+  return GQ_OK;
+}
+
+gq_status gq_clear_stats(gq_queue* q, void* stream) {
+  if (!q) return GQ_ERR_INVALID;
+  HIP_OK(hipMemsetAsync(q->dev.stats, 0, S_NUM * sizeof(uint64_t), S(stream)));
+  return GQ_OK;
+}
+
+gq_status gq_check_error(gq_queue* q, void* stream) {
+  if (!q) return GQ_ERR_INVALID;
+  uint64_t e = 0;
+  HIP_OK(hipMemcpyAsync(&e, q->dev.err, sizeof(e), hipMemcpyDeviceToHost, S(stream)));
+  HIP_OK(hipStreamSynchronize(S(stream)));
+  if (e == 0) return GQ_OK;
+  return (gq_status)(-(int64_t)e);
+}
+
+// ---- drivers ----------------------------------------------------------------
+static Rec make_rec(const gq_history* h) {
+  Rec r;
+  memset(&r, 0, sizeof(r));
+  if (h) {
+    r.h = *h;
+    r.on = true;
+  }
+  return r;
+}
+
+gq_status gq_run_mix(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t ops_per_lane,
+                     uint64_t* d_counts, const gq_history* hist, void* stream) {
+  if (!q || !d_counts || lanes == 0 || lanes % kBlock || lanes > q->k) return GQ_ERR_INVALID;
+  if (hist && (!hist->val || !hist->call || !hist->ret || !hist->opst)) return GQ_ERR_INVALID;
+  if (q->kind != GQ_LFQ) return GQ_ERR_INVALID;
+  const dim3 grid(lanes / kBlock), block(kBlock);
+  const Rec rec = make_rec(hist);
+  if (hist)
+    LAUNCH((k_mix<GQ_LFQ, true>), grid, block, 0, S(stream), q->dev, seed,
+                       ops_per_lane, d_counts, rec);
+  else
+    LAUNCH((k_mix<GQ_LFQ, false>), grid, block, 0, S(stream), q->dev, seed,
+                       ops_per_lane, d_counts, rec);
+  HIP_OK(hipGetLastError());
+  return GQ_OK;
+}
+
+gq_status gq_run_balanced(gq_queue* q, uint32_t lanes, uint32_t rounds, uint64_t* d_counts,
+                          const gq_history* hist, void* stream) {
+  if (!q || !d_counts || lanes == 0 || lanes % kBlock || lanes > q->k) return GQ_ERR_INVALID;
+  if (hist && (!hist->val || !hist->call || !hist->ret || !hist->opst)) return GQ_ERR_INVALID;
+  if (q->kind != GQ_LFQ) return GQ_ERR_INVALID;
+  const dim3 grid(lanes / kBlock), block(kBlock);
+  const Rec rec = make_rec(hist);
+  if (hist)
+    LAUNCH((k_balanced<GQ_LFQ, true>), grid, block, 0, S(stream), q->dev, rounds,
+                       d_counts, rec);
+  else
+    LAUNCH((k_balanced<GQ_LFQ, false>), grid, block, 0, S(stream), q->dev, rounds,
+                       d_counts, rec);
+  HIP_OK(hipGetLastError());
+  return GQ_OK;
+}
+
+static gq_status resident_blocks_of(const void* fn, uint32_t block, uint32_t* out) {
+  int dev = 0, cus = 0, nb = 0;
+  HIP_OK(hipGetDevice(&dev));
+  HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, (int)block, 0));
+  *out = (uint32_t)(nb * cus);
+  return GQ_OK;
+}
+
+gq_status gq_run_prodcons(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t block,
+                          const uint8_t* d_lane_role, uint32_t items_per_producer,
+                          uint64_t target, uint32_t log2_inv_p, uint32_t token_mode,
+                          uint32_t jitter, uint64_t max_rounds, uint64_t* d_counts,
+                          const gq_history* hist, void* stream) {
+  if (!q || !d_counts || !d_lane_role || lanes == 0 || block == 0 || block > 1024 ||
+      block % 64 || lanes % block || log2_inv_p > 63 || token_mode > 1 || lanes > q->k)
+    return GQ_ERR_INVALID;
+  if (hist && (!hist->val || !hist->call || !hist->ret || !hist->opst)) return GQ_ERR_INVALID;
+  if (q->kind != GQ_LFQ) return GQ_ERR_INVALID;
+  const void* fn = hist ? (const void*)k_prodcons<GQ_LFQ, true> : (const void*)k_prodcons<GQ_LFQ, false>;
+  uint32_t resident = 0;
+  gq_status st = resident_blocks_of(fn, block, &resident);
+  if (st != GQ_OK) return st;
+  if (lanes / block > resident) return GQ_ERR_RESIDENCY;
+  // The shared "taken" counter sits in the queue's control block.
+  uint64_t* taken = (uint64_t*)(q->buf + OFF_TAKEN);
+  HIP_OK(hipMemsetAsync(taken, 0, sizeof(uint64_t), S(stream)));
+  const Rec rec = make_rec(hist);
+  const dim3 grid(lanes / block), blk(block);
+  if (hist)
+    LAUNCH((k_prodcons<GQ_LFQ, true>), grid, blk, 0, S(stream), q->dev, seed,
+                       d_lane_role, items_per_producer, target, log2_inv_p, token_mode, jitter,
+                       max_rounds, taken, d_counts, rec);
+  else
+    LAUNCH((k_prodcons<GQ_LFQ, false>), grid, blk, 0, S(stream), q->dev, seed,
+                       d_lane_role, items_per_producer, target, log2_inv_p, token_mode, jitter,
+                       max_rounds, taken, d_counts, rec);
+  HIP_OK(hipGetLastError());
+  return GQ_OK;
+}
+
+gq_status gq_run_script(gq_queue* q, uint32_t lanes, uint32_t spread, const uint8_t* d_ops,
+                        const uint64_t* d_args, const uint16_t* d_pause, const uint32_t* d_n_ops,
+                        uint32_t max_ops, const gq_history* hist, void* stream) {
+  if (!q || !hist || !d_ops || !d_args || !d_pause || !d_n_ops || lanes == 0 || lanes > 1024 ||
+      lanes > q->k)
+    return GQ_ERR_INVALID;
+  if (!hist->val || !hist->call || !hist->ret || !hist->opst || hist->per_lane < max_ops)
+    return GQ_ERR_INVALID;
+  if (q->kind != GQ_LFQ) return GQ_ERR_INVALID;
+  const Rec rec = make_rec(hist);
+  const dim3 grid(spread ? lanes : 1), block(spread ? 64 : ((lanes + 63) / 64) * 64);
+  LAUNCH((k_script<GQ_LFQ>), grid, block, 0, S(stream), q->dev, lanes, spread, d_ops,
+                     d_args, d_pause, d_n_ops, max_ops, rec);
+  HIP_OK(hipGetLastError());
+  return GQ_OK;
+}
+
+// ---- probes -------------------------------------------------------------------
+static uint64_t* probe_sink() {
+  static uint64_t* s = nullptr;
+  if (!s) (void)hipMalloc(&s, 256);
+  return s;
+}
+
+gq_status gq_probe_faa(uint64_t* d_ctr, uint32_t lanes, uint32_t iters, uint32_t per_lane,
+                       void* stream) {
+  if (!d_ctr || lanes == 0 || lanes % kBlock) return GQ_ERR_INVALID;
+  LAUNCH(k_probe_faa, dim3(lanes / kBlock), dim3(kBlock), 0, S(stream), d_ctr, iters,
+                     per_lane, probe_sink());
+  HIP_OK(hipGetLastError());
+  return GQ_OK;
+}
+
+gq_status gq_probe_cas(uint64_t* d_slots, uint64_t nslots, uint32_t stride_bytes, uint32_t lanes,
+                       uint32_t iters, void* stream) {
+  if (!d_slots || nslots == 0 || lanes == 0 || lanes % kBlock || stride_bytes < 8 ||
+      stride_bytes % 8)
+    return GQ_ERR_INVALID;
+  LAUNCH(k_probe_cas, dim3(lanes / kBlock), dim3(kBlock), 0, S(stream), d_slots,
+                     nslots, stride_bytes / 8, iters, probe_sink());
+  HIP_OK(hipGetLastError());
+  return GQ_OK;
+}
+
+gq_status gq_probe_copy(uint64_t* d_dst, const uint64_t* d_src, uint64_t n, void* stream) {
+  if (!d_dst || !d_src) return GQ_ERR_INVALID;
+  const uint32_t grid = grid_for(n / 2, kBlock, 8192);
+  LAUNCH(k_probe_copy, dim3(grid), dim3(kBlock), 0, S(stream), d_dst, d_src, n);
+  HIP_OK(hipGetLastError());
+  return GQ_OK;
+}
+
+gq_status gq_probe_fence(uint64_t* d_lines, uint32_t lanes, uint32_t iters, uint32_t mode,
+                         void* stream) {
+  if (!d_lines || lanes == 0 || lanes % kBlock || mode > 3) return GQ_ERR_INVALID;
+  LAUNCH(k_probe_fence, dim3(lanes / kBlock), dim3(kBlock), 0, S(stream), d_lines,
+                     iters, mode);
+  HIP_OK(hipGetLastError());
+  return GQ_OK;
+}
+
+gq_status gq_resident_blocks(const char* kernel, gq_kind kind, uint32_t block,
+                             uint32_t* out_blocks) {
+  if (!kernel || !out_blocks || block == 0 || block > 1024) return GQ_ERR_INVALID;
+  if (kind != GQ_LFQ) return GQ_ERR_INVALID;
+  const void* fn = nullptr;
+  if (!strcmp(kernel, "mix")) fn = (const void*)k_mix<GQ_LFQ, false>;
+  else if (!strcmp(kernel, "prodcons")) fn = (const void*)k_prodcons<GQ_LFQ, false>;
+  else return GQ_ERR_INVALID;
+  return resident_blocks_of(fn, block, out_blocks);
+}
+
+gq_status gq_device_info(uint32_t* cus, uint32_t* wave, char* name, uint32_t len) {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  hipDeviceProp_t p;
+  HIP_OK(hipGetDeviceProperties(&p, dev));
+  if (cus) *cus = (uint32_t)p.multiProcessorCount;
+  if (wave) *wave = (uint32_t)p.warpSize;
+  if (name && len) {
+    strncpy(name, p.gcnArchName, len - 1);
+    name[len - 1] = 0;
+  }
+  return GQ_OK;
+}
+
+}  // extern "C"

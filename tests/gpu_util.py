@@ -1,0 +1,74 @@
+"""Helpers for the GPU parity tests: run the HIP path through the C ABI, turn
+recorded histories into oracle inputs, and apply the oracle's checks."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+
+def torch():
+    import torch as t
+    return t
+
+
+def u64(t):
+    """torch int64 CUDA/CPU tensor -> numpy uint64."""
+    return t.cpu().numpy().view(np.uint64)
+
+
+def drain_fifo(q, max_items: int):
+    """Sequential drain by one lane (FIFO order), via the scripted driver."""
+    import paper_2606_01693_amd as gq
+    T = torch()
+    k = max_items + 1
+    ops = T.ones(k, dtype=T.uint8, device="cuda")
+    args = T.zeros(k, dtype=T.int64, device="cuda")
+    pauses = T.zeros(k, dtype=T.int16, device="cuda")
+    n_ops = T.tensor([k], dtype=T.int32, device="cuda")
+    h = gq.History(1, k)
+    q.run_script(1, False, ops, args, pauses, n_ops, k, h)
+    T.cuda.synchronize()
+    proc, op, st, val, call, ret, _ = h.to_numpy()
+    ok = st == gq.GQ_OK
+    first_empty = int(np.argmin(ok)) if not ok.all() else len(ok)
+    assert not ok[first_empty:].any(), "an OK dequeue after EMPTY in a sequential drain"
+    assert first_empty < k, "drain did not reach EMPTY"
+    return val[:first_empty].copy()
+
+
+def history(h) -> tuple:
+    proc, op, st, val, call, ret, overflow = h.to_numpy()
+    return oracle.History(proc, op, st, val, call, ret), overflow
+
+
+def assert_clean(rep: dict, hist: oracle.History = None, drain=(), prefill=(), tag="case"):
+    """Fail with the full report; keep the failing history for offline study
+    (under gpurun_out/, which GPU runs bring back)."""
+    if all(v == 0 for v in rep.values()):
+        return
+    if hist is not None:
+        import os
+        os.makedirs("gpurun_out", exist_ok=True)
+        np.savez_compressed(os.path.join("gpurun_out", f"fail_{tag}.npz"), proc=hist.proc,
+                            op=hist.op, st=hist.st, val=hist.val, call=hist.call,
+                            ret=hist.ret, drain=np.asarray(drain, dtype=np.uint64),
+                            prefill=np.asarray(prefill, dtype=np.uint64))
+    import pytest
+    pytest.fail("oracle report: " + ", ".join(f"{k}={v}" for k, v in rep.items()))
+
+
+def check_history(hist: oracle.History, drain, prefill=(), capacity=0, token_shift=32,
+                  producer_order=True):
+    """Conservation + per-producer order + violation scan.  Returns a report
+    dict; every entry must be zero."""
+    put = np.concatenate([np.asarray(prefill, dtype=np.uint64), hist.enq_ok()])
+    out = np.concatenate([hist.deq_ok(), np.asarray(drain, dtype=np.uint64)])
+    rep = {}
+    rep.update({"cons_" + k: v for k, v in oracle.conservation(put, out).items()})
+    if producer_order:
+        rep.update({"po_" + k: v for k, v in oracle.producer_order(hist, token_shift).items()})
+    rep.update({"v_" + k: v for k, v in
+                oracle.violation_scan(hist, prefill=prefill, drain=drain,
+                                      capacity=capacity).items()})
+    return rep

@@ -1,0 +1,76 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/*.h declares, and its pure-host logic (sizes,
+parameter validation, status strings) behaves as documented."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2606_01693_amd", "libgq.so")
+
+
+def declared_functions():
+    names = set()
+    for h in ("gq.h", "gq_bench.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(gq_[a-z_0-9]+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "build first: __graft_entry__.build()"
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+
+
+def test_binding_signature_table_covers_header():
+    from paper_2606_01693_amd import _binding
+    assert sorted(_binding.EXPORTS) == sorted(n for n in declared_functions())
+
+
+def test_library_loads_and_status_strings():
+    from paper_2606_01693_amd import _binding as b
+    L = b.load_library()
+    assert L.gq_status_str(0) == b"ok"
+    assert L.gq_status_str(-5).startswith(b"cycle")
+    assert L.gq_status_str(99) == b"unknown status"
+
+
+@pytest.mark.parametrize("cap,width,ok", [
+    (1, 8, False), (2, 8, True), (3, 8, False), (1 << 20, 8, True), (1 << 30, 4, True),
+    (1 << 31, 8, False), (1024, 2, False), (1024, 4, True),
+])
+def test_required_bytes_validation(cap, width, ok):
+    from paper_2606_01693_amd import _binding as b
+    L = b.load_library()
+    out = ctypes.c_uint64(0)
+    rc = L.gq_required_bytes(0, cap, width, 1, None, ctypes.byref(out))
+    assert (rc == 0) == ok
+    if ok:
+        # two 2n-entry rings of 8-byte words plus n payload cells at least
+        assert out.value >= 2 * (2 * cap * 8) + cap * width
+
+
+def test_required_bytes_padded_layout_is_larger():
+    from paper_2606_01693_amd import _binding as b
+    compact = b.required_bytes("lfq", 1 << 16, 8, 1, "remap")
+    padded = b.required_bytes("lfq", 1 << 16, 8, 1, "padded")
+    assert padded - compact >= 2 * (2 << 16) * (128 - 8)
+
+
+def test_null_arguments_rejected():
+    from paper_2606_01693_amd import _binding as b
+    L = b.load_library()
+    assert L.gq_required_bytes(0, 1024, 8, 1, None, None) == b.GQ_ERR_INVALID
+    assert L.gq_destroy(None) == b.GQ_ERR_INVALID
+    assert L.gq_create(0, 1024, 8, 1, None, None, 0, None) == b.GQ_ERR_INVALID
+    assert L.gq_enqueue_batch(None, None, 0, None, None, None) == b.GQ_ERR_INVALID
+    assert L.gq_run_mix(None, 0, 256, 1, None, None, None) == b.GQ_ERR_INVALID

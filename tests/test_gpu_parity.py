@@ -1,0 +1,317 @@
+"""GPU parity tests: the HIP queues, called through the C ABI, against the CPU
+oracle.  A concurrent queue has many correct outcomes, so parity means: the
+recorded history passes the oracle's checks (exact multiset conservation,
+per-producer order, violation scan, exhaustive linearizability on tiny runs),
+and deterministic shapes (one lane; one wavefront into a quiescent queue;
+stream-ordered batches) match the sequential FIFO replay exactly."""
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_util import assert_clean, check_history, drain_fifo, history, torch, u64
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["lfq"]
+BOUNDED = {"lfq": True, "wfq": True, "ymc": False}
+
+
+def make_queue(kind, n, width=8, lanes=1024, slot_mode="remap"):
+    import paper_2606_01693_amd as gq
+    print(f"[case] kind={kind} n={n} width={width} lanes={lanes} slots={slot_mode}", flush=True)
+    return gq.Queue(kind, n, item_width=width, max_threads=lanes, slot_mode=slot_mode)
+
+
+def cap_of(kind, n):
+    return n if BOUNDED[kind] else 0
+
+
+def all_zero(rep):
+    return all(v == 0 for v in rep.values())
+
+
+def prefill(q, items):
+    T = torch()
+    if len(items) == 0:
+        return
+    t = T.tensor(np.asarray(items, dtype=np.uint64).view(np.int64), device="cuda")
+    # one lane enqueues them in list order
+    ops = T.zeros(len(items), dtype=T.uint8, device="cuda")
+    pauses = T.zeros(len(items), dtype=T.int16, device="cuda")
+    n_ops = T.tensor([len(items)], dtype=T.int32, device="cuda")
+    import paper_2606_01693_amd as gq
+    h = gq.History(1, len(items))
+    q.run_script(1, False, ops, t, pauses, n_ops, len(items), h)
+    T.cuda.synchronize()
+    _, _, s, _, _, _, _ = h.to_numpy()
+    assert (s == gq.GQ_OK).all()
+
+
+# ---------------------------------------------------------------------------
+# Deterministic shapes: exact equality with the sequential replay
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("n,seed", [(2, 0), (4, 1), (16, 2), (1024, 3)])
+def test_single_lane_equals_replay(kind, n, seed):
+    import paper_2606_01693_amd as gq
+    T = torch()
+    q = make_queue(kind, n)
+    rng = np.random.default_rng(seed)
+    m = 3000
+    ops = (rng.random(m) < 0.45).astype(np.uint8)  # 55% enqueues: reaches FULL often
+    ops = 1 - ops
+    args = np.arange(1, m + 1, dtype=np.uint64) * 7919
+    h = gq.History(1, m)
+    q.run_script(1, False, T.tensor(ops, device="cuda"),
+                 T.tensor(args.view(np.int64), device="cuda"),
+                 T.zeros(m, dtype=T.int16, device="cuda"),
+                 T.tensor([m], dtype=T.int32, device="cuda"), m, h)
+    T.cuda.synchronize()
+    assert q.check_error() == gq.GQ_OK
+    proc, op, st, val, call, ret, _ = h.to_numpy()
+    exp_st, exp_val, resid = oracle.fifo_replay(ops, args, capacity=cap_of(kind, n))
+    assert np.array_equal(st, exp_st)
+    assert np.array_equal(val, exp_val)
+    assert np.array_equal(drain_fifo(q, n + 8 if BOUNDED[kind] else m), resid)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("seed", range(6))
+def test_single_wave_closed_form(kind, seed):
+    """Lemma 1: one wavefront's active lanes take consecutive tickets in lane
+    order, so into a quiescent queue the r-th active enqueuer's item is the
+    r-th dequeued, and the r-th active dequeuer receives it."""
+    import paper_2606_01693_amd as gq
+    T = torch()
+    q = make_queue(kind, 256)
+    rng = np.random.default_rng(100 + seed)
+    enq_mask = rng.random(64) < rng.uniform(0.1, 1.0)
+    enq_mask[rng.integers(0, 64)] = True
+    deq_mask = rng.random(64) < rng.uniform(0.1, 1.0)
+    deq_mask[rng.integers(0, 64)] = True
+    args = (np.arange(64, dtype=np.uint64) + 1) * 1000003
+
+    def run(mask, op):
+        n_ops = T.tensor(mask.astype(np.int32), device="cuda")
+        h = gq.History(64, 1)
+        q.run_script(64, False, T.full((64,), op, dtype=T.uint8, device="cuda"),
+                     T.tensor(args.view(np.int64), device="cuda"),
+                     T.zeros(64, dtype=T.int16, device="cuda"), n_ops, 1, h)
+        T.cuda.synchronize()
+        return h.to_numpy()
+
+    proc, op, st, val, _, _, _ = run(enq_mask, 0)
+    assert (st == gq.GQ_OK).all() and np.array_equal(proc, np.nonzero(enq_mask)[0])
+    proc, op, st, val, _, _, _ = run(deq_mask, 1)
+    enq_lanes = np.nonzero(enq_mask)[0]
+    deq_lanes = np.nonzero(deq_mask)[0]
+    assert np.array_equal(proc, deq_lanes)
+    for r, lane in enumerate(deq_lanes):
+        if r < len(enq_lanes):
+            assert st[r] == gq.GQ_OK and val[r] == args[enq_lanes[r]], (r, lane)
+        else:
+            assert st[r] == gq.GQ_EMPTY
+    rest = drain_fifo(q, 64)
+    assert np.array_equal(rest, args[enq_lanes[len(deq_lanes):]])
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_batches_are_stream_ordered(kind):
+    import paper_2606_01693_amd as gq
+    T = torch()
+    n = 1 << 12
+    q = make_queue(kind, n)
+    a = T.arange(1, 1001, dtype=T.int64, device="cuda")
+    b = T.arange(5001, 6501, dtype=T.int64, device="cuda")
+    nok = T.zeros(1, dtype=T.int64, device="cuda")
+    q.enqueue_batch(a, num_ok=nok)
+    q.enqueue_batch(b, num_ok=nok)
+    out1 = T.zeros(1000, dtype=T.int64, device="cuda")
+    out2 = T.zeros(1501, dtype=T.int64, device="cuda")
+    st2 = T.zeros(1501, dtype=T.uint8, device="cuda")
+    q.dequeue_batch(out1, num_ok=nok)
+    q.dequeue_batch(out2, st2, num_ok=nok)
+    T.cuda.synchronize()
+    assert int(nok) == 2500 + 2500
+    assert sorted(out1.cpu().tolist()) == list(range(1, 1001))
+    s2 = st2.cpu().numpy()
+    assert (s2 == gq.GQ_OK).sum() == 1500 and (s2 == gq.GQ_EMPTY).sum() == 1
+    assert sorted(out2.cpu().numpy()[s2 == gq.GQ_OK].tolist()) == list(range(5001, 6501))
+    assert q.check_error() == gq.GQ_OK
+
+
+@pytest.mark.parametrize("kind", [k for k in KINDS if BOUNDED[k]])
+@pytest.mark.parametrize("n", [2, 64, 1 << 14])
+def test_batch_capacity_exact(kind, n):
+    """With only enqueues in flight, a linearizable bounded queue accepts
+    exactly capacity - size of them; with only dequeues, it returns exactly
+    size items."""
+    import paper_2606_01693_amd as gq
+    T = torch()
+    q = make_queue(kind, n)
+    m = n + 100
+    items = T.arange(1, m + 1, dtype=T.int64, device="cuda")
+    st = T.zeros(m, dtype=T.uint8, device="cuda")
+    q.enqueue_batch(items, st)
+    out = T.zeros(n + 50, dtype=T.int64, device="cuda")
+    st2 = T.zeros(n + 50, dtype=T.uint8, device="cuda")
+    q.dequeue_batch(out, st2)
+    T.cuda.synchronize()
+    s = st.cpu().numpy()
+    assert (s == gq.GQ_OK).sum() == n and (s == gq.GQ_FULL).sum() == 100
+    s2 = st2.cpu().numpy()
+    assert (s2 == gq.GQ_OK).sum() == n and (s2 == gq.GQ_EMPTY).sum() == 50
+    accepted = items.cpu().numpy()[s == gq.GQ_OK]
+    assert sorted(out.cpu().numpy()[s2 == gq.GQ_OK].tolist()) == sorted(accepted.tolist())
+
+
+# ---------------------------------------------------------------------------
+# Small producer/consumer configuration: capacity 2^10, uint32 payload
+# (pid << 20) | seq, 8 producer + 8 consumer wavefronts, 2^16 operations.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("run", range(5))
+def test_c1_role_split(kind, run):
+    import paper_2606_01693_amd as gq
+    T = torch()
+    seed = workloads.run_seed(1, run)
+    n, lanes, block = 1 << 10, 1024, 256
+    q = make_queue(kind, n, width=4, lanes=lanes)
+    prod_waves = workloads.producer_waves(seed, 16, 8)
+    role = np.repeat(np.where(prod_waves, 0, 1), 64).astype(np.uint8)
+    counts = T.zeros(4, dtype=T.int64, device="cuda")
+    h = gq.History(lanes, 1 << 14)
+    q.run_prodcons(seed, lanes, block, T.tensor(role, device="cuda"), 64, 32768, 0, 1, counts, h,
+                   max_rounds=1 << 22)
+    T.cuda.synchronize()
+    assert q.check_error() == gq.GQ_OK
+    c = counts.cpu().tolist()
+    assert c[0] == 32768 and c[1] == 32768
+    hist, overflow = history(h)
+    assert overflow == 0
+    drain = drain_fifo(q, n)
+    rep = check_history(hist, drain, capacity=n, token_shift=20)
+    assert_clean(rep, hist, drain, tag=f"c1split_{kind}_{run}")
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("run", range(5))
+def test_c1_balanced(kind, run):
+    """Every lane enqueues then dequeues, 32 times; 1024 lanes on capacity 1024:
+    no FULL can occur, and no dequeue can find the queue empty (each dequeuer
+    completed its own enqueue first)."""
+    import paper_2606_01693_amd as gq
+    T = torch()
+    n, lanes = 1 << 10, 1024
+    q = make_queue(kind, n, width=8, lanes=lanes)
+    counts = T.zeros(4, dtype=T.int64, device="cuda")
+    h = gq.History(lanes, 64)
+    q.run_balanced(lanes, 32, counts, h)
+    T.cuda.synchronize()
+    assert q.check_error() == gq.GQ_OK
+    assert counts.cpu().tolist() == [32768, 32768, 0, 0]
+    hist, overflow = history(h)
+    assert overflow == 0
+    drain = drain_fifo(q, n)
+    rep = check_history(hist, drain, capacity=n)
+    assert_clean(rep, hist, drain, tag=f"c1bal_{kind}_{run}")
+
+
+# ---------------------------------------------------------------------------
+# Tiny concurrent runs: exhaustive linearizability search
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("chunk", range(4))
+def test_tiny_histories_linearizable(kind, chunk):
+    import paper_2606_01693_amd as gq
+    T = torch()
+    rng = random.Random(4242 + chunk)
+    n = 4
+    q = make_queue(kind, n, lanes=64)
+    max_ops = 4
+    for trial in range(50):
+        q.reset()
+        # prefill tokens come from a producer id no lane uses
+        pre = [(0xFFFF << 32) | (i + 1) for i in range(rng.randint(0, 2))]
+        prefill(q, pre)
+        lanes = rng.randint(2, 6)
+        ops = np.zeros((lanes, max_ops), dtype=np.uint8)
+        args = np.zeros((lanes, max_ops), dtype=np.uint64)
+        pauses = np.zeros((lanes, max_ops), dtype=np.int16)
+        n_ops = np.array([rng.randint(2, max_ops) for _ in range(lanes)], dtype=np.int32)
+        for g in range(lanes):
+            for r in range(max_ops):
+                ops[g, r] = rng.random() < 0.5
+                args[g, r] = (g << 32) | (r + 1)
+                pauses[g, r] = rng.randint(0, 40)
+        h = gq.History(lanes, max_ops)
+        q.run_script(lanes, True, T.tensor(ops.ravel(), device="cuda"),
+                     T.tensor(args.ravel().view(np.int64), device="cuda"),
+                     T.tensor(pauses.ravel(), device="cuda"),
+                     T.tensor(n_ops, device="cuda"), max_ops, h)
+        T.cuda.synchronize()
+        hist, _ = history(h)
+        drain = drain_fifo(q, n + 4)
+        rows = list(zip(hist.proc.tolist(), hist.op.tolist(), hist.st.tolist(),
+                        hist.val.tolist(), hist.call.tolist(), hist.ret.tolist()))
+        tmax = int(hist.ret.max()) + 10
+        rows += [(99, 1, 0, int(v), tmax + 2 * k, tmax + 2 * k + 1) for k, v in enumerate(drain)]
+        rows += [(99, 1, 1, 0, tmax + 2 * len(drain), tmax + 2 * len(drain) + 1)]
+        ok, _ = oracle.check_linearizable(rows, capacity=n if BOUNDED[kind] else None,
+                                          prefill=pre)
+        assert ok, (trial, rows, pre)
+        rep = check_history(hist, drain, prefill=pre, capacity=cap_of(kind, n))
+        assert_clean(rep, hist, drain, pre, tag=f"tiny_{kind}_{chunk}_{trial}")
+    assert q.check_error() == gq.GQ_OK
+
+
+# ---------------------------------------------------------------------------
+# Mixed 50/50 workload with recorded histories
+# ---------------------------------------------------------------------------
+def run_mix_checked(kind, n, lanes, ops, seed, slot_mode="remap", do_prefill=True):
+    import paper_2606_01693_amd as gq
+    T = torch()
+    q = make_queue(kind, n, lanes=lanes, slot_mode=slot_mode)
+    pre = []
+    if do_prefill:
+        pre = [int(workloads.token(0xFFFFFFFF, i)) for i in range(n // 2)]
+        prefill(q, pre)
+    counts = T.zeros(4, dtype=T.int64, device="cuda")
+    h = gq.History(lanes, ops)
+    q.run_mix(seed, lanes, ops, counts, h)
+    T.cuda.synchronize()
+    assert q.check_error() == gq.GQ_OK
+    hist, overflow = history(h)
+    assert overflow == 0
+    # the device drew the same roles as the shared workload definition
+    roles = workloads.mix_roles(seed, lanes, ops).ravel()
+    assert np.array_equal(hist.op, roles)
+    c = counts.cpu().tolist()
+    assert c[0] == int(((hist.op == 0) & (hist.st == 0)).sum())
+    drain = drain_fifo(q, n if BOUNDED[kind] else len(pre) + c[0])
+    assert len(drain) == len(pre) + c[0] - c[1]
+    rep = check_history(hist, drain, prefill=pre, capacity=cap_of(kind, n))
+    assert_clean(rep, hist, drain, pre, tag=f"mix_{kind}_{n}_{lanes}_{ops}_{slot_mode}")
+    return c
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("n,lanes,ops", [(2, 1024, 64), (4, 4096, 32), (64, 16384, 16),
+                                         (1 << 10, 16384, 32), (1 << 16, 65536, 16)])
+def test_mix_history(kind, n, lanes, ops):
+    run_mix_checked(kind, n, lanes, ops, workloads.run_seed(2, n))
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_mix_history_padded_slots(kind):
+    run_mix_checked(kind, 1 << 10, 16384, 32, workloads.run_seed(2, 77), slot_mode="padded")
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_mix_full_size(kind):
+    """The benchmark's configuration: capacity 2^20, 2048 x 256 lanes, 2^26
+    operations, prefill n/2; the full history is checked."""
+    run_mix_checked(kind, 1 << 20, 2048 * 256, 128, workloads.run_seed(2, 0))
