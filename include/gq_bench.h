@@ -72,28 +72,30 @@ gq_status gq_run_prodcons(gq_queue *q, uint64_t seed, uint32_t lanes, uint32_t b
                           uint32_t jitter, uint64_t max_rounds, uint64_t *d_counts,
                           const gq_history *hist, void *stream);
 
-/* Scripted run for small linearizability tests: lane g (of `lanes`, one
- * workgroup of `block` lanes per `lanes_per_block` active lanes) executes
- * n_ops[g] operations from ops[g * max_ops ...] (0 enqueue, 1 dequeue) with
- * arguments args[...], pausing pause[g * max_ops + r] sleep units before op r.
- * Results go to hist (required).  Lanes are spread one per wavefront when
- * spread != 0, so that they really run concurrently.                          */
+/* Scripted run for small linearizability tests: lane g (< lanes <= 1024)
+ * executes n_ops[g] operations from ops[g * max_ops ...] (0 enqueue,
+ * 1 dequeue) with arguments args[...], pausing pause[g * max_ops + r] sleep
+ * units before op r.  Results go to hist (required, per_lane >= max_ops).
+ * spread != 0: each lane runs alone in its own wavefront (one workgroup per
+ * lane), so lanes really run concurrently; spread == 0: all lanes form one
+ * workgroup, and lanes of one wavefront issue their operations together.      */
 gq_status gq_run_script(gq_queue *q, uint32_t lanes, uint32_t spread, const uint8_t *d_ops,
                         const uint64_t *d_args, const uint16_t *d_pause,
                         const uint32_t *d_n_ops, uint32_t max_ops, const gq_history *hist,
                         void *stream);
 
 /* ---- roofline probes -------------------------------------------------------
- * R_ctr: lanes/64 wavefronts each perform `iters` fetch-and-adds on the single
- *   counter *d_ctr: one per wavefront (per_lane = 0, the WaveFAA shape) or one
- *   per lane (per_lane = 1).
+ * R_ctr: lanes/64 wavefronts each perform `iters` fetch-and-adds on a counter:
+ *   wavefront w uses d_ctr[(w mod ncounters) * spacing_bytes / 8] (the buffer
+ *   must hold ncounters * spacing_bytes bytes); one FAA per wavefront
+ *   (per_lane = 0, the WaveFAA shape) or one per lane (per_lane = 1).
  * R_slot: each lane performs `iters` 64-bit CAS on slot (t mod nslots), t from
  *   a per-lane ticket sequence, slots spaced stride_bytes apart.
  * Copy: d_dst[i] = d_src[i] for n 64-bit words (HBM stream bandwidth).
  * Fence: each wavefront performs `iters` agent-scope release+acquire fences
  *   around one relaxed atomic store to its own line.                          */
 gq_status gq_probe_faa(uint64_t *d_ctr, uint32_t lanes, uint32_t iters, uint32_t per_lane,
-                       void *stream);
+                       uint32_t ncounters, uint32_t spacing_bytes, void *stream);
 gq_status gq_probe_cas(uint64_t *d_slots, uint64_t nslots, uint32_t stride_bytes,
                        uint32_t lanes, uint32_t iters, void *stream);
 gq_status gq_probe_copy(uint64_t *d_dst, const uint64_t *d_src, uint64_t n, void *stream);

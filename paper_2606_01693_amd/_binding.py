@@ -98,7 +98,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gq_run_balanced": [P, U32, U32, P, P, P],
         "gq_run_prodcons": [P, U64, U32, U32, P, U32, U64, U32, U32, U32, U64, P, P, P],
         "gq_run_script": [P, U32, U32, P, P, P, P, U32, P, P],
-        "gq_probe_faa": [P, U32, U32, U32, P],
+        "gq_probe_faa": [P, U32, U32, U32, U32, U32, P],
         "gq_probe_cas": [P, U64, U32, U32, U32, P],
         "gq_probe_copy": [P, P, U64, P],
         "gq_probe_fence": [P, U32, U32, U32, P],
@@ -301,9 +301,11 @@ class Queue:
 
 
 # ---- probes and device info ---------------------------------------------------
-def probe_faa(ctr, lanes: int, iters: int, per_lane: bool, stream=None):
-    _check(lib().gq_probe_faa(_ptr(ctr), lanes, iters, 1 if per_lane else 0, _stream(stream)),
-           "gq_probe_faa")
+def probe_faa(ctr, lanes: int, iters: int, per_lane: bool, ncounters: int = 1,
+              spacing_bytes: int = 256, stream=None):
+    assert ctr.numel() * ctr.element_size() >= ncounters * spacing_bytes
+    _check(lib().gq_probe_faa(_ptr(ctr), lanes, iters, 1 if per_lane else 0, ncounters,
+                              spacing_bytes, _stream(stream)), "gq_probe_faa")
 
 
 def probe_cas(slots, nslots: int, stride_bytes: int, lanes: int, iters: int, stream=None):

@@ -324,11 +324,14 @@ __global__ void k_script(gq_dev q, uint32_t lanes, uint32_t spread, const uint8_
 }
 
 // ---- roofline probes ---------------------------------------------------------
-__global__ void k_probe_faa(uint64_t* ctr, uint32_t iters, uint32_t per_lane, uint64_t* sink) {
+__global__ void k_probe_faa(uint64_t* ctr, uint32_t iters, uint32_t per_lane, uint32_t ncounters,
+                            uint32_t spacing_words, uint64_t* sink) {
+  const uint64_t w = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) / 64;
+  uint64_t* c = ctr + (w % ncounters) * spacing_words;
   uint64_t acc = 0;
   for (uint32_t i = 0; i < iters; i++) {
-    if (per_lane) acc += faa(ctr, 1ull);
-    else acc += wave_faa(ctr, 1ull);
+    if (per_lane) acc += faa(c, 1ull);
+    else acc += wave_faa(c, 1ull);
   }
   if (acc == 0x5555555555555555ull) sink[0] = acc;
 }
@@ -708,10 +711,11 @@ static uint64_t* probe_sink() {
 }
 
 gq_status gq_probe_faa(uint64_t* d_ctr, uint32_t lanes, uint32_t iters, uint32_t per_lane,
-                       void* stream) {
-  if (!d_ctr || lanes == 0 || lanes % kBlock) return GQ_ERR_INVALID;
-  LAUNCH(k_probe_faa, dim3(lanes / kBlock), dim3(kBlock), 0, S(stream), d_ctr, iters,
-                     per_lane, probe_sink());
+                       uint32_t ncounters, uint32_t spacing_bytes, void* stream) {
+  if (!d_ctr || lanes == 0 || lanes % kBlock || ncounters == 0 || spacing_bytes % 8)
+    return GQ_ERR_INVALID;
+  LAUNCH(k_probe_faa, dim3(lanes / kBlock), dim3(kBlock), 0, S(stream), d_ctr, iters, per_lane,
+         ncounters, spacing_bytes / 8, probe_sink());
   HIP_OK(hipGetLastError());
   return GQ_OK;
 }
