@@ -135,6 +135,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--kind", default="lfq", choices=["lfq"])
     ap.add_argument("--slot-mode", default="remap", choices=["remap", "padded"])
+    ap.add_argument("--fenced", action="store_true",
+                    help="release/acquire payload hand-off instead of the atomic exchange")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-probes", action="store_true")
     args = ap.parse_args()
@@ -151,7 +153,7 @@ def main():
     info = gq.device_info()
     log(f"[bench] device {info}")
     q = gq.Queue(args.kind, CAP, item_width=ITEM_BYTES, max_threads=LANES,
-                 slot_mode=args.slot_mode)
+                 slot_mode=args.slot_mode, fenced=args.fenced)
     pre = torch.arange(1, CAP // 2 + 1, dtype=torch.int64, device="cuda") | (0xFFFFFFFF << 32)
     q.enqueue_batch(pre)
     counts = torch.zeros(4, dtype=torch.int64, device="cuda")
@@ -207,7 +209,7 @@ def main():
         "config": {
             "workload": f"G-LFQ ({args.kind}) mixed 50/50, capacity 2^20, uint64 payload, "
                         f"2^26 op attempts per step, 2048 WGs x 256 lanes, prefill n/2, "
-                        f"slots={args.slot_mode}",
+                        f"slots={args.slot_mode}, hand-off={'fenced' if args.fenced else 'atomic'}",
             "capacity": CAP, "lanes": LANES, "ops_per_lane": OPS_PER_LANE,
             "parallelism": "single GPU",
         },

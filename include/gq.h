@@ -59,13 +59,27 @@ typedef enum { GQ_LFQ = 0, GQ_WFQ = 1, GQ_WFQ_YMC = 2 } gq_kind;
  *   GQ_SLOTS_PADDED  one entry per 128-byte line.                            */
 typedef enum { GQ_SLOTS_REMAP = 0, GQ_SLOTS_PADDED = 1 } gq_slot_mode;
 
+/* Option flags (gq_options.flags):
+ *   GQ_OPT_FENCED      hand payloads over with an agent-scope release on the
+ *                      install CAS and an acquire on the consume, and plain
+ *                      payload stores/loads (the default instead exchanges the
+ *                      payload atomically and waits for it before the install,
+ *                      which needs no cache write-back or invalidate);
+ *   GQ_OPT_WFQ_TUNING  use wfq_patience_enq / wfq_patience_deq / wfq_help_delay
+ *                      instead of the defaults (16 / 64 / 64); a patience of 0
+ *                      sends every G-WFQ operation down the slow path.          */
+#define GQ_OPT_FENCED 1u
+#define GQ_OPT_WFQ_TUNING 2u
+
 typedef struct gq_options {
     uint32_t slot_mode;        /* gq_slot_mode; default GQ_SLOTS_REMAP        */
-    uint32_t reserved0;
+    uint32_t flags;            /* GQ_OPT_* bits                               */
     uint64_t ymc_pool_cells;   /* G-WFQ-YMC pool size; 0 = 2^27 cells or
                                   16 * capacity, whichever is larger          */
-    uint32_t flags;            /* reserved, must be 0                          */
-    uint32_t reserved1;
+    uint32_t wfq_patience_enq; /* fast-path attempts before the slow path     */
+    uint32_t wfq_patience_deq;
+    uint32_t wfq_help_delay;   /* D: operations between peer-record checks    */
+    uint32_t reserved;
 } gq_options;
 
 /* ---- device view ---------------------------------------------------------
@@ -78,6 +92,7 @@ typedef struct gq_ring_view {
     uint64_t *tail;            /* 64-bit ticket counter (own 256-byte line)   */
     int64_t *threshold;        /* signed empty-detection counter              */
     void *records;             /* G-WFQ per-lane request records, else NULL   */
+    uint64_t *owner;           /* G-WFQ per-slot installer hints, else NULL   */
 } gq_ring_view;
 
 typedef struct gq_dev {
@@ -86,7 +101,7 @@ typedef struct gq_dev {
     uint32_t log2_cap;         /* log2(capacity)                              */
     uint32_t slot_mode;        /* gq_slot_mode                                */
     uint32_t max_threads;      /* k: lane ids passed to the device API < k    */
-    uint32_t pad0;
+    uint32_t flags;            /* GQ_OPT_* bits in effect                     */
     uint64_t capacity;         /* n                                           */
     void *data;                /* n payload cells of item_width bytes         */
     gq_ring_view aq;           /* ring of allocated indices                   */
@@ -97,6 +112,10 @@ typedef struct gq_dev {
     uint64_t ymc_pool_cells;
     uint64_t *ymc_ctr;         /* G-WFQ-YMC T at [0], H at [32]               */
     void *ymc_handles;         /* G-WFQ-YMC per-lane handles                  */
+    uint32_t patience_enq;     /* G-WFQ fast-path attempts                    */
+    uint32_t patience_deq;
+    uint32_t help_delay;       /* G-WFQ help delay D                          */
+    uint32_t pad1;
 } gq_dev;
 
 typedef struct gq_stats {
@@ -106,15 +125,17 @@ typedef struct gq_stats {
     uint64_t tickets;          /* tickets taken (all counters)                */
     uint64_t slow_enter;       /* G-WFQ / YMC slow-path entries               */
     uint64_t helps;            /* peer requests helped                        */
+    uint64_t scans;            /* G-WFQ record scans to finalize an enqueue   */
 } gq_stats;
 
 /* Bytes of device memory a queue with these parameters needs.
  * capacity: power of two in [2, 2^30]; item_width: 4 or 8;
- * max_threads (k): number of distinct lane ids that may call the queue
- * (G-WFQ and G-WFQ-YMC keep one record per lane id; G-LFQ ignores it).
+ * max_threads (k): the most lanes that may operate on the queue at once, in
+ * [1, 2^20); G-WFQ and G-WFQ-YMC keep one record per lane id (< k), and all
+ * queues size their empty-detection threshold for k concurrent lanes.
  * opts may be NULL.  Returns GQ_ERR_INVALID on bad parameters and
- * GQ_ERR_CYCLE_BOUND when G-WFQ's 8-bit cycle tags cannot satisfy
- * R > D*k/n + 6 (Section III-C, Lemma 4, with D = 64).                       */
+ * GQ_ERR_CYCLE_BOUND when G-WFQ's cycle tags (R = 2^15) cannot satisfy
+ * R > D*k/n + 6 (Section III-C, Lemma 4).                                    */
 gq_status gq_required_bytes(gq_kind kind, uint64_t capacity, uint32_t item_width,
                             uint32_t max_threads, const gq_options *opts,
                             uint64_t *bytes);

@@ -39,16 +39,34 @@ class GQError(RuntimeError):
         super().__init__(f"{what}: {status_str(status)} ({status})")
 
 
+GQ_OPT_FENCED = 1
+GQ_OPT_WFQ_TUNING = 2
+
+
 class _Options(ctypes.Structure):
-    _fields_ = [("slot_mode", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
-                ("ymc_pool_cells", ctypes.c_uint64), ("flags", ctypes.c_uint32),
-                ("reserved1", ctypes.c_uint32)]
+    _fields_ = [("slot_mode", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("ymc_pool_cells", ctypes.c_uint64), ("wfq_patience_enq", ctypes.c_uint32),
+                ("wfq_patience_deq", ctypes.c_uint32), ("wfq_help_delay", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+def make_options(slot_mode="remap", fenced=False, ymc_pool_cells=0, patience=None,
+                 help_delay=None) -> _Options:
+    flags = GQ_OPT_FENCED if fenced else 0
+    pe, pd, hd = 16, 64, 64
+    if patience is not None or help_delay is not None:
+        flags |= GQ_OPT_WFQ_TUNING
+        if patience is not None:
+            pe, pd = (patience, patience) if isinstance(patience, int) else patience
+        if help_delay is not None:
+            hd = help_delay
+    return _Options(SLOT_MODES[slot_mode], flags, ymc_pool_cells, pe, pd, hd, 0)
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("ok_enq", "ok_deq", "full", "empty", "cas_fail", "tickets", "slow_enter",
-                 "helps")]
+                 "helps", "scans")]
 
 
 class _History(ctypes.Structure):
@@ -59,18 +77,21 @@ class _History(ctypes.Structure):
 
 class _RingView(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_void_p), ("head", ctypes.c_void_p), ("tail", ctypes.c_void_p),
-                ("threshold", ctypes.c_void_p), ("records", ctypes.c_void_p)]
+                ("threshold", ctypes.c_void_p), ("records", ctypes.c_void_p),
+                ("owner", ctypes.c_void_p)]
 
 
 class _DevView(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_uint32), ("item_width", ctypes.c_uint32),
                 ("log2_cap", ctypes.c_uint32), ("slot_mode", ctypes.c_uint32),
-                ("max_threads", ctypes.c_uint32), ("pad0", ctypes.c_uint32),
+                ("max_threads", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("capacity", ctypes.c_uint64), ("data", ctypes.c_void_p),
                 ("aq", _RingView), ("fq", _RingView), ("err", ctypes.c_void_p),
                 ("stats", ctypes.c_void_p), ("ymc_cells", ctypes.c_void_p),
                 ("ymc_pool_cells", ctypes.c_uint64), ("ymc_ctr", ctypes.c_void_p),
-                ("ymc_handles", ctypes.c_void_p)]
+                ("ymc_handles", ctypes.c_void_p), ("patience_enq", ctypes.c_uint32),
+                ("patience_deq", ctypes.c_uint32), ("help_delay", ctypes.c_uint32),
+                ("pad1", ctypes.c_uint32)]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -151,8 +172,8 @@ def _ptr(t) -> ctypes.c_void_p:
 
 
 def required_bytes(kind: str, capacity: int, item_width: int = 8, max_threads: int = 1,
-                   slot_mode: str = "remap", ymc_pool_cells: int = 0) -> int:
-    o = _Options(SLOT_MODES[slot_mode], 0, ymc_pool_cells, 0, 0)
+                   slot_mode: str = "remap", ymc_pool_cells: int = 0, **opts) -> int:
+    o = make_options(slot_mode, ymc_pool_cells=ymc_pool_cells, **opts)
     out = ctypes.c_uint64(0)
     _check(lib().gq_required_bytes(KINDS[kind], capacity, item_width, max_threads,
                                    ctypes.byref(o), ctypes.byref(out)), "gq_required_bytes")
@@ -169,6 +190,7 @@ class Stats:
     tickets: int
     slow_enter: int
     helps: int
+    scans: int
 
 
 class History:
@@ -211,14 +233,19 @@ class Queue:
     """One device queue.  kind: 'lfq' | 'wfq' | 'ymc'."""
 
     def __init__(self, kind: str, capacity: int, item_width: int = 8, max_threads: int = 1,
-                 slot_mode: str = "remap", ymc_pool_cells: int = 0):
+                 slot_mode: str = "remap", ymc_pool_cells: int = 0, fenced: bool = False,
+                 patience=None, help_delay=None):
         torch = _torch()
         self.kind, self.capacity, self.item_width = kind, capacity, item_width
         self.max_threads = max_threads
-        nbytes = required_bytes(kind, capacity, item_width, max_threads, slot_mode, ymc_pool_cells)
+        self._opts = make_options(slot_mode, fenced, ymc_pool_cells, patience, help_delay)
+        o = self._opts
+        out = ctypes.c_uint64(0)
+        _check(lib().gq_required_bytes(KINDS[kind], capacity, item_width, max_threads,
+                                       ctypes.byref(o), ctypes.byref(out)), "gq_required_bytes")
+        nbytes = int(out.value)
         # torch owns the memory; 256-byte alignment comes from the caching allocator
         self._buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        self._opts = _Options(SLOT_MODES[slot_mode], 0, ymc_pool_cells, 0, 0)
         h = ctypes.c_void_p(0)
         _check(lib().gq_create(KINDS[kind], capacity, item_width, max_threads,
                                ctypes.byref(self._opts), _ptr(self._buf), nbytes,

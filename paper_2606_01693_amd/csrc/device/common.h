@@ -54,6 +54,12 @@ __device__ __forceinline__ bool cas_acqrel(uint64_t* p, uint64_t& expected, uint
   return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_ACQ_REL,
                                               __ATOMIC_ACQUIRE, GQ_AGENT);
 }
+__device__ __forceinline__ uint64_t xchg(uint64_t* p, uint64_t v) {
+  return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, GQ_AGENT);
+}
+__device__ __forceinline__ uint32_t xchg(uint32_t* p, uint32_t v) {
+  return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, GQ_AGENT);
+}
 __device__ __forceinline__ uint64_t faa(uint64_t* p, uint64_t v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, GQ_AGENT);
 }
@@ -72,6 +78,14 @@ __device__ __forceinline__ uint64_t f_or(uint64_t* p, uint64_t v) {
 __device__ __forceinline__ uint64_t f_and(uint64_t* p, uint64_t v) {
   return __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, GQ_AGENT);
 }
+// Wait until every memory operation this wavefront issued has completed
+// (returned its value or been acknowledged).  Orders an atomic that must be
+// performed before a later one without any cache maintenance.
+__device__ __forceinline__ void wait_mem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// Keep a value live in a register so the atomic producing it returns it.
+template <typename T>
+__device__ __forceinline__ void keep(T v) { asm volatile("" ::"v"(v)); }
+
 __device__ __forceinline__ void fence_acq() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 __device__ __forceinline__ void fence_rel() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 __device__ __forceinline__ void fence_acqrel() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent"); }
@@ -168,6 +182,6 @@ __device__ __forceinline__ void latch_error(uint64_t* err, uint64_t code) {
 }
 
 // Statistics slots (gq_stats order).
-enum StatSlot { S_OK_ENQ = 0, S_OK_DEQ, S_FULL, S_EMPTY, S_CAS_FAIL, S_TICKETS, S_SLOW, S_HELPS, S_NUM };
+enum StatSlot { S_OK_ENQ = 0, S_OK_DEQ, S_FULL, S_EMPTY, S_CAS_FAIL, S_TICKETS, S_SLOW, S_HELPS, S_SCAN, S_NUM };
 
 }  // namespace gq

@@ -103,8 +103,7 @@ __device__ __forceinline__ void catchup(const Ring& r, uint64_t t, uint64_t h) {
 }
 
 // Inner enqueue of index `idx` (Algorithm 1, TryEnq, retried until success).
-// The install CAS is a release so that the payload written before it is
-// visible to whoever consumes the entry.  An index ring never holds more than
+// RELEASE makes the install CAS an agent-scope release (fenced hand-off).  An index ring never holds more than
 // n indices in 2n slots, so the retry loop ends (lock-freedom, Section III-B).
 template <bool RELEASE>
 __device__ __forceinline__ bool ring_enq(const Ring& r, uint32_t idx, uint32_t& cas_fail,
@@ -138,7 +137,8 @@ __device__ __forceinline__ bool ring_enq(const Ring& r, uint32_t idx, uint32_t& 
 }
 
 // Inner dequeue (Algorithm 1, TryDeq, retried until an index or EMPTY).
-// Returns the index, or BOT for EMPTY.  Consume is an atomic XOR that turns
+// Returns the index, or BOT for EMPTY.  ACQUIRE makes Consume an agent-scope
+// acquire (fenced hand-off).  Consume is an atomic XOR that turns
 // the index field into BOTC and leaves Cycle/Safe alone; between install and
 // consume only Safe can change, so the XOR is exact.
 template <bool ACQUIRE>
@@ -182,13 +182,51 @@ __device__ __forceinline__ uint32_t ring_deq(const Ring& r, uint32_t& cas_fail, 
   }
 }
 
+// ---- payload hand-off -----------------------------------------------------
+// The enqueuer owning index idx writes data[idx]; the dequeuer that consumes
+// idx reads it.  Default: the write is an agent-scope atomic exchange that has
+// completed (wait_mem) before the install CAS is issued, and the read is an
+// agent-scope atomic load issued after the consumer saw the installed entry,
+// and completed before idx is returned to the free ring.  All three accesses
+// are atomics on one cell ordered by those waits, so no L2 write-back or
+// invalidate is needed.  With GQ_OPT_FENCED the hand-off instead uses plain
+// accesses with an agent-scope release on the install and an acquire on the
+// consume (Section III's ordering, at the cost of cache maintenance).
+template <bool FENCED>
+__device__ __forceinline__ void payload_put(const gq_dev& q, uint32_t idx, uint64_t item) {
+  if (FENCED) {
+    if (q.item_width == 8) ((uint64_t*)q.data)[idx] = item;
+    else ((uint32_t*)q.data)[idx] = (uint32_t)item;
+  } else {
+    if (q.item_width == 8) keep(xchg((uint64_t*)q.data + idx, item));
+    else keep(xchg((uint32_t*)q.data + idx, (uint32_t)item));
+    wait_mem();
+  }
+}
+
+template <bool FENCED>
+__device__ __forceinline__ uint64_t payload_get(const gq_dev& q, uint32_t idx) {
+  uint64_t v;
+  if (FENCED) {
+    v = q.item_width == 8 ? ((const uint64_t*)q.data)[idx]
+                          : (uint64_t)((const uint32_t*)q.data)[idx];
+  } else {
+    v = q.item_width == 8 ? ld((const uint64_t*)q.data + idx)
+                          : (uint64_t)ld((const uint32_t*)q.data + idx);
+    keep(v);
+    wait_mem();  // the read completes before idx goes back to the free ring
+  }
+  return v;
+}
+
 // ---- outer queue (Section III-B: indices move through aq/fq) -------------
 // enqueue: idx <- fq.deq (EMPTY means FULL); data[idx] <- x; aq.enq(idx).
 // dequeue: idx <- aq.deq (EMPTY means EMPTY); x <- data[idx]; fq.enq(idx).
-__device__ __forceinline__ int enqueue(const gq_dev& q, uint64_t item, uint32_t& cas_fail) {
+template <bool FENCED>
+__device__ __forceinline__ int enqueue_impl(const gq_dev& q, uint64_t item, uint32_t& cas_fail) {
   const Ring fq = make_ring(q.fq, q);
   const Ring aq = make_ring(q.aq, q);
-  // The payload store below depends on idx, and the previous holder of idx
+  // The payload write below depends on idx, and the previous holder of idx
   // finished reading the cell before releasing idx into fq: no acquire needed.
   const uint32_t idx = ring_deq<false>(fq, cas_fail, q.err);
   if (idx == BOT) return GQ_FULL;
@@ -196,25 +234,34 @@ __device__ __forceinline__ int enqueue(const gq_dev& q, uint64_t item, uint32_t&
     latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
     return GQ_FULL;
   }
-  if (q.item_width == 8) ((uint64_t*)q.data)[idx] = item;
-  else ((uint32_t*)q.data)[idx] = (uint32_t)item;
-  ring_enq<true>(aq, idx, cas_fail, q.err);  // release publishes the payload
+  payload_put<FENCED>(q, idx, item);
+  ring_enq<FENCED>(aq, idx, cas_fail, q.err);
   return GQ_OK;
 }
 
-__device__ __forceinline__ int dequeue(const gq_dev& q, uint64_t* item, uint32_t& cas_fail) {
+template <bool FENCED>
+__device__ __forceinline__ int dequeue_impl(const gq_dev& q, uint64_t* item, uint32_t& cas_fail) {
   const Ring aq = make_ring(q.aq, q);
   const Ring fq = make_ring(q.fq, q);
-  const uint32_t idx = ring_deq<true>(aq, cas_fail, q.err);  // acquire pairs with the install
+  const uint32_t idx = ring_deq<FENCED>(aq, cas_fail, q.err);
   if (idx == BOT) return GQ_EMPTY;
   if (idx >= q.capacity) {  // never taken: guards the payload array
     latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
     return GQ_EMPTY;
   }
-  *item = q.item_width == 8 ? ((const uint64_t*)q.data)[idx]
-                            : (uint64_t)((const uint32_t*)q.data)[idx];
-  ring_enq<true>(fq, idx, cas_fail, q.err);  // release: the read above completes first
+  *item = payload_get<FENCED>(q, idx);
+  ring_enq<FENCED>(fq, idx, cas_fail, q.err);
   return GQ_OK;
+}
+
+__device__ __forceinline__ int enqueue(const gq_dev& q, uint64_t item, uint32_t& cas_fail) {
+  return (q.flags & GQ_OPT_FENCED) ? enqueue_impl<true>(q, item, cas_fail)
+                                   : enqueue_impl<false>(q, item, cas_fail);
+}
+
+__device__ __forceinline__ int dequeue(const gq_dev& q, uint64_t* item, uint32_t& cas_fail) {
+  return (q.flags & GQ_OPT_FENCED) ? dequeue_impl<true>(q, item, cas_fail)
+                                   : dequeue_impl<false>(q, item, cas_fail);
 }
 
 }  // namespace lfq

@@ -51,10 +51,10 @@ enum : uint64_t {
   OFF_FQ_TAIL = 4 * kLine,
   OFF_FQ_THR = 5 * kLine,
   OFF_ERR = 6 * kLine,
-  OFF_STATS = 7 * kLine,   // 8 words
-  OFF_YMC_T = 8 * kLine,
-  OFF_YMC_H = 9 * kLine,
-  OFF_TAKEN = 10 * kLine,  // producer/consumer driver: items taken so far
+  OFF_STATS = 7 * kLine,   // up to 32 words
+  OFF_YMC_T = 9 * kLine,
+  OFF_YMC_H = 10 * kLine,
+  OFF_TAKEN = 11 * kLine,  // producer/consumer driver: items taken so far
 };
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
@@ -66,10 +66,16 @@ inline uint32_t ilog2(uint64_t x) {
 }
 
 struct Layout {
-  uint64_t slots_aq, slots_fq, data, rec_aq, rec_fq, ymc_pool, ymc_handles, total;
+  uint64_t slots_aq, slots_fq, data, rec_aq, rec_fq, own_aq, own_fq, ymc_pool, ymc_handles, total;
 };
 
-bool kind_supported(gq_kind kind) { return kind == GQ_LFQ; }
+bool kind_supported(gq_kind kind) { return kind == GQ_LFQ || kind == GQ_WFQ; }
+
+// G-WFQ: Lemma 4 requires R > D*k/n + 6 for the cycle range R of its tags.
+bool wfq_cycle_bound_ok(uint64_t n, uint64_t k, uint64_t D) {
+  const uint64_t R = 1ull << wfq::TAG_BITS;
+  return D * k < (R - 6) * n;
+}
 
 gq_status plan(gq_kind kind, uint64_t n, uint32_t w, uint32_t k, const gq_options* o,
                Layout* L) {
@@ -77,7 +83,15 @@ gq_status plan(gq_kind kind, uint64_t n, uint32_t w, uint32_t k, const gq_option
   if (!is_pow2(n) || n < 2 || n > (1ull << 30)) return GQ_ERR_INVALID;
   if (w != 4 && w != 8) return GQ_ERR_INVALID;
   if (k == 0 || k > (1u << 24)) return GQ_ERR_INVALID;
-  if (o && (o->flags != 0 || o->slot_mode > GQ_SLOTS_PADDED)) return GQ_ERR_INVALID;
+  if (o && ((o->flags & ~(GQ_OPT_FENCED | GQ_OPT_WFQ_TUNING)) || o->slot_mode > GQ_SLOTS_PADDED))
+    return GQ_ERR_INVALID;
+  if (kind == GQ_WFQ) {
+    if (k >= (1u << wfq::TID_BITS)) return GQ_ERR_INVALID;
+    const bool tuned = o && (o->flags & GQ_OPT_WFQ_TUNING);
+    const uint64_t D = tuned ? o->wfq_help_delay : 64;
+    if (tuned && D == 0) return GQ_ERR_INVALID;
+    if (!wfq_cycle_bound_ok(n, k, D)) return GQ_ERR_CYCLE_BOUND;
+  }
   const uint32_t mode = o ? o->slot_mode : GQ_SLOTS_REMAP;
   const uint64_t slot_bytes = 2 * n * (mode == GQ_SLOTS_PADDED ? 128 : 8);
   uint64_t off = kCtrlBytes;
@@ -87,7 +101,17 @@ gq_status plan(gq_kind kind, uint64_t n, uint32_t w, uint32_t k, const gq_option
   off = align_up(off + slot_bytes, 4096);
   L->data = off;
   off = align_up(off + n * w, 4096);
-  L->rec_aq = L->rec_fq = L->ymc_pool = L->ymc_handles = 0;
+  L->rec_aq = L->rec_fq = L->own_aq = L->own_fq = L->ymc_pool = L->ymc_handles = 0;
+  if (kind == GQ_WFQ) {
+    L->rec_aq = off;
+    off = align_up(off + (uint64_t)k * sizeof(wfq::Rec), 4096);
+    L->rec_fq = off;
+    off = align_up(off + (uint64_t)k * sizeof(wfq::Rec), 4096);
+    L->own_aq = off;
+    off = align_up(off + 2 * n * 8, 4096);
+    L->own_fq = off;
+    off = align_up(off + 2 * n * 8, 4096);
+  }
   L->total = off;
   return GQ_OK;
 }
@@ -112,6 +136,47 @@ __global__ void k_init_lfq(gq_dev q) {
     st(q.aq.threshold, (int64_t)-1);
     st(q.fq.head, 0ull);
     st(q.fq.tail, q.capacity);
+    st(q.fq.threshold, lfq::threshold_reset(q));
+    st(q.err, 0ull);
+    for (int s = 0; s < S_NUM; s++) st(q.stats + s, 0ull);
+  }
+}
+
+// G-WFQ rings: entries all ones in every field (Note = Cycle = -1 mod R,
+// Safe, Enq, BOT); the free ring holds <Note -1, cycle 0, Safe, Enq, i> in
+// slots [0, n).  Global words <counter, NULL>; records cleared, sequence
+// numbers start at 1, help counters staggered by lane.
+__global__ void k_init_wfq(gq_dev q) {
+  const uint64_t two_n = 2 * q.capacity;
+  const lfq::Ring aq = lfq::make_ring(q.aq, q);
+  const lfq::Ring fq = lfq::make_ring(q.fq, q);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t g0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  for (uint64_t j = g0; j < two_n; j += stride) {
+    st(aq.at(j), ~0ull);
+    st(fq.at(j), j < q.capacity ? wfq::e_make(wfq::TAG_MASK, 0, true, true, (uint32_t)j) : ~0ull);
+    st(q.aq.owner + j, 0ull);
+    st(q.fq.owner + j, 0ull);
+  }
+  wfq::Rec* ra = (wfq::Rec*)q.aq.records;
+  wfq::Rec* rf = (wfq::Rec*)q.fq.records;
+  for (uint64_t t = g0; t < q.max_threads; t += stride) {
+    for (wfq::Rec* R : {ra + t, rf + t}) {
+      st(&R->local, 0ull);
+      st(&R->init, 0ull);
+      st(&R->index, 0ull);
+      st(&R->req, 0ull);
+      st(&R->next_seq, 1ull);
+      const uint64_t peer = (t + 1) % q.max_threads;
+      st(&R->help, (peer << 32) | (t % (q.help_delay ? q.help_delay : 1)));
+    }
+  }
+  if (g0 == 0) {
+    st(q.aq.head, 0ull);
+    st(q.aq.tail, 0ull);
+    st(q.aq.threshold, (int64_t)-1);
+    st(q.fq.head, 0ull);
+    st(q.fq.tail, q.capacity << wfq::TID_BITS);
     st(q.fq.threshold, lfq::threshold_reset(q));
     st(q.err, 0ull);
     for (int s = 0; s < S_NUM; s++) st(q.stats + s, 0ull);
@@ -394,11 +459,14 @@ struct gq_queue {
 static hipStream_t S(void* s) { return (hipStream_t)s; }
 
 static gq_status launch_init(gq_queue* q, hipStream_t s) {
-  const uint64_t slots = 2 * q->n;
+  const uint64_t slots = 2 * q->n > q->k ? 2 * q->n : q->k;
   const uint32_t grid = grid_for(slots, kBlock, 4096);
   switch (q->kind) {
     case GQ_LFQ:
       LAUNCH(k_init_lfq, dim3(grid), dim3(kBlock), 0, s, q->dev);
+      break;
+    case GQ_WFQ:
+      LAUNCH(k_init_wfq, dim3(grid), dim3(kBlock), 0, s, q->dev);
       break;
     default:
       return GQ_ERR_INVALID;
@@ -431,7 +499,8 @@ static void launch_deq(gq_queue* q, void* out, uint64_t m, uint8_t* st, uint64_t
                      nok);
 }
 
-extern "C" {
+// The exported functions below were declared extern "C" in gq.h/gq_bench.h,
+// so their definitions keep C linkage; helper templates stay C++.
 
 const char* gq_status_str(gq_status s) {
   switch (s) {
@@ -500,7 +569,16 @@ gq_status gq_create(gq_kind kind, uint64_t capacity, uint32_t item_width, uint32
   d.log2_cap = ilog2(capacity);
   d.slot_mode = q->opt.slot_mode;
   d.max_threads = max_threads;
+  d.flags = q->opt.flags;
   d.capacity = capacity;
+  d.patience_enq = 16;
+  d.patience_deq = 64;
+  d.help_delay = 64;
+  if (q->opt.flags & GQ_OPT_WFQ_TUNING) {
+    d.patience_enq = q->opt.wfq_patience_enq;
+    d.patience_deq = q->opt.wfq_patience_deq;
+    d.help_delay = q->opt.wfq_help_delay;
+  }
   d.data = q->buf + L.data;
   d.aq.slots = (uint64_t*)(q->buf + L.slots_aq);
   d.aq.head = (uint64_t*)(q->buf + OFF_AQ_HEAD);
@@ -510,6 +588,12 @@ gq_status gq_create(gq_kind kind, uint64_t capacity, uint32_t item_width, uint32
   d.fq.head = (uint64_t*)(q->buf + OFF_FQ_HEAD);
   d.fq.tail = (uint64_t*)(q->buf + OFF_FQ_TAIL);
   d.fq.threshold = (int64_t*)(q->buf + OFF_FQ_THR);
+  if (kind == GQ_WFQ) {
+    d.aq.records = q->buf + L.rec_aq;
+    d.fq.records = q->buf + L.rec_fq;
+    d.aq.owner = (uint64_t*)(q->buf + L.own_aq);
+    d.fq.owner = (uint64_t*)(q->buf + L.own_fq);
+  }
   d.err = (uint64_t*)(q->buf + OFF_ERR);
   d.stats = (uint64_t*)(q->buf + OFF_STATS);
   d.ymc_ctr = (uint64_t*)(q->buf + OFF_YMC_T);
@@ -545,6 +629,7 @@ gq_status gq_enqueue_batch(gq_queue* q, const void* d_items, uint64_t m, uint8_t
   if (m == 0) return GQ_OK;
   switch (q->kind) {
     case GQ_LFQ: launch_enq<GQ_LFQ>(q, d_items, m, d_status, d_num_ok, S(stream)); break;
+    case GQ_WFQ: launch_enq<GQ_WFQ>(q, d_items, m, d_status, d_num_ok, S(stream)); break;
     default: return GQ_ERR_INVALID;
   }
   HIP_OK(hipGetLastError());
@@ -557,6 +642,7 @@ gq_status gq_dequeue_batch(gq_queue* q, void* d_out, uint64_t m, uint8_t* d_stat
   if (m == 0) return GQ_OK;
   switch (q->kind) {
     case GQ_LFQ: launch_deq<GQ_LFQ>(q, d_out, m, d_status, d_num_ok, S(stream)); break;
+    case GQ_WFQ: launch_deq<GQ_WFQ>(q, d_out, m, d_status, d_num_ok, S(stream)); break;
     default: return GQ_ERR_INVALID;
   }
   HIP_OK(hipGetLastError());
@@ -582,6 +668,7 @@ gq_status gq_read_stats(gq_queue* q, gq_stats* out, void* stream) {
   out->tickets = s[S_TICKETS];
   out->slow_enter = s[S_SLOW];
   out->helps = s[S_HELPS];
+  out->scans = s[S_SCAN];
   return GQ_OK;
 }
 
@@ -611,36 +698,47 @@ static Rec make_rec(const gq_history* h) {
   return r;
 }
 
+// Each driver is instantiated per queue kind; KIND_SWITCH picks the
+// instantiation for q->kind.
+#define KIND_SWITCH(kind, CALL)                      \
+  switch (kind) {                                    \
+    case GQ_LFQ: { constexpr int K = GQ_LFQ; CALL; } break; \
+    case GQ_WFQ: { constexpr int K = GQ_WFQ; CALL; } break; \
+    default: return GQ_ERR_INVALID;                  \
+  }
+
+template <int KIND>
+static void launch_mix(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t ops, uint64_t* counts,
+                       const gq_history* hist, hipStream_t s) {
+  const dim3 grid(lanes / kBlock), block(kBlock);
+  const Rec rec = make_rec(hist);
+  if (hist) LAUNCH((k_mix<KIND, true>), grid, block, 0, s, q->dev, seed, ops, counts, rec);
+  else LAUNCH((k_mix<KIND, false>), grid, block, 0, s, q->dev, seed, ops, counts, rec);
+}
+
 gq_status gq_run_mix(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t ops_per_lane,
                      uint64_t* d_counts, const gq_history* hist, void* stream) {
   if (!q || !d_counts || lanes == 0 || lanes % kBlock || lanes > q->k) return GQ_ERR_INVALID;
   if (hist && (!hist->val || !hist->call || !hist->ret || !hist->opst)) return GQ_ERR_INVALID;
-  if (q->kind != GQ_LFQ) return GQ_ERR_INVALID;
-  const dim3 grid(lanes / kBlock), block(kBlock);
-  const Rec rec = make_rec(hist);
-  if (hist)
-    LAUNCH((k_mix<GQ_LFQ, true>), grid, block, 0, S(stream), q->dev, seed,
-                       ops_per_lane, d_counts, rec);
-  else
-    LAUNCH((k_mix<GQ_LFQ, false>), grid, block, 0, S(stream), q->dev, seed,
-                       ops_per_lane, d_counts, rec);
+  KIND_SWITCH(q->kind, launch_mix<K>(q, seed, lanes, ops_per_lane, d_counts, hist, S(stream)));
   HIP_OK(hipGetLastError());
   return GQ_OK;
+}
+
+template <int KIND>
+static void launch_balanced(gq_queue* q, uint32_t lanes, uint32_t rounds, uint64_t* counts,
+                            const gq_history* hist, hipStream_t s) {
+  const dim3 grid(lanes / kBlock), block(kBlock);
+  const Rec rec = make_rec(hist);
+  if (hist) LAUNCH((k_balanced<KIND, true>), grid, block, 0, s, q->dev, rounds, counts, rec);
+  else LAUNCH((k_balanced<KIND, false>), grid, block, 0, s, q->dev, rounds, counts, rec);
 }
 
 gq_status gq_run_balanced(gq_queue* q, uint32_t lanes, uint32_t rounds, uint64_t* d_counts,
                           const gq_history* hist, void* stream) {
   if (!q || !d_counts || lanes == 0 || lanes % kBlock || lanes > q->k) return GQ_ERR_INVALID;
   if (hist && (!hist->val || !hist->call || !hist->ret || !hist->opst)) return GQ_ERR_INVALID;
-  if (q->kind != GQ_LFQ) return GQ_ERR_INVALID;
-  const dim3 grid(lanes / kBlock), block(kBlock);
-  const Rec rec = make_rec(hist);
-  if (hist)
-    LAUNCH((k_balanced<GQ_LFQ, true>), grid, block, 0, S(stream), q->dev, rounds,
-                       d_counts, rec);
-  else
-    LAUNCH((k_balanced<GQ_LFQ, false>), grid, block, 0, S(stream), q->dev, rounds,
-                       d_counts, rec);
+  KIND_SWITCH(q->kind, launch_balanced<K>(q, lanes, rounds, d_counts, hist, S(stream)));
   HIP_OK(hipGetLastError());
   return GQ_OK;
 }
@@ -654,6 +752,27 @@ static gq_status resident_blocks_of(const void* fn, uint32_t block, uint32_t* ou
   return GQ_OK;
 }
 
+template <int KIND>
+static const void* prodcons_fn(bool hist) {
+  return hist ? (const void*)k_prodcons<KIND, true> : (const void*)k_prodcons<KIND, false>;
+}
+
+template <int KIND>
+static void launch_prodcons(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t block,
+                            const uint8_t* role, uint32_t quota, uint64_t target,
+                            uint32_t log2_inv_p, uint32_t token_mode, uint32_t jitter,
+                            uint64_t max_rounds, uint64_t* taken, uint64_t* counts,
+                            const gq_history* hist, hipStream_t s) {
+  const Rec rec = make_rec(hist);
+  const dim3 grid(lanes / block), blk(block);
+  if (hist)
+    LAUNCH((k_prodcons<KIND, true>), grid, blk, 0, s, q->dev, seed, role, quota, target,
+           log2_inv_p, token_mode, jitter, max_rounds, taken, counts, rec);
+  else
+    LAUNCH((k_prodcons<KIND, false>), grid, blk, 0, s, q->dev, seed, role, quota, target,
+           log2_inv_p, token_mode, jitter, max_rounds, taken, counts, rec);
+}
+
 gq_status gq_run_prodcons(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t block,
                           const uint8_t* d_lane_role, uint32_t items_per_producer,
                           uint64_t target, uint32_t log2_inv_p, uint32_t token_mode,
@@ -663,8 +782,8 @@ gq_status gq_run_prodcons(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t b
       block % 64 || lanes % block || log2_inv_p > 63 || token_mode > 1 || lanes > q->k)
     return GQ_ERR_INVALID;
   if (hist && (!hist->val || !hist->call || !hist->ret || !hist->opst)) return GQ_ERR_INVALID;
-  if (q->kind != GQ_LFQ) return GQ_ERR_INVALID;
-  const void* fn = hist ? (const void*)k_prodcons<GQ_LFQ, true> : (const void*)k_prodcons<GQ_LFQ, false>;
+  const void* fn = nullptr;
+  KIND_SWITCH(q->kind, fn = prodcons_fn<K>(hist != nullptr));
   uint32_t resident = 0;
   gq_status st = resident_blocks_of(fn, block, &resident);
   if (st != GQ_OK) return st;
@@ -672,18 +791,21 @@ gq_status gq_run_prodcons(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t b
   // The shared "taken" counter sits in the queue's control block.
   uint64_t* taken = (uint64_t*)(q->buf + OFF_TAKEN);
   HIP_OK(hipMemsetAsync(taken, 0, sizeof(uint64_t), S(stream)));
-  const Rec rec = make_rec(hist);
-  const dim3 grid(lanes / block), blk(block);
-  if (hist)
-    LAUNCH((k_prodcons<GQ_LFQ, true>), grid, blk, 0, S(stream), q->dev, seed,
-                       d_lane_role, items_per_producer, target, log2_inv_p, token_mode, jitter,
-                       max_rounds, taken, d_counts, rec);
-  else
-    LAUNCH((k_prodcons<GQ_LFQ, false>), grid, blk, 0, S(stream), q->dev, seed,
-                       d_lane_role, items_per_producer, target, log2_inv_p, token_mode, jitter,
-                       max_rounds, taken, d_counts, rec);
+  KIND_SWITCH(q->kind, launch_prodcons<K>(q, seed, lanes, block, d_lane_role, items_per_producer,
+                                          target, log2_inv_p, token_mode, jitter, max_rounds,
+                                          taken, d_counts, hist, S(stream)));
   HIP_OK(hipGetLastError());
   return GQ_OK;
+}
+
+template <int KIND>
+static void launch_script(gq_queue* q, uint32_t lanes, uint32_t spread, const uint8_t* ops,
+                          const uint64_t* args, const uint16_t* pauses, const uint32_t* n_ops,
+                          uint32_t max_ops, const gq_history* hist, hipStream_t s) {
+  const Rec rec = make_rec(hist);
+  const dim3 grid(spread ? lanes : 1), block(spread ? 64 : ((lanes + 63) / 64) * 64);
+  LAUNCH((k_script<KIND>), grid, block, 0, s, q->dev, lanes, spread, ops, args, pauses, n_ops,
+         max_ops, rec);
 }
 
 gq_status gq_run_script(gq_queue* q, uint32_t lanes, uint32_t spread, const uint8_t* d_ops,
@@ -694,11 +816,8 @@ gq_status gq_run_script(gq_queue* q, uint32_t lanes, uint32_t spread, const uint
     return GQ_ERR_INVALID;
   if (!hist->val || !hist->call || !hist->ret || !hist->opst || hist->per_lane < max_ops)
     return GQ_ERR_INVALID;
-  if (q->kind != GQ_LFQ) return GQ_ERR_INVALID;
-  const Rec rec = make_rec(hist);
-  const dim3 grid(spread ? lanes : 1), block(spread ? 64 : ((lanes + 63) / 64) * 64);
-  LAUNCH((k_script<GQ_LFQ>), grid, block, 0, S(stream), q->dev, lanes, spread, d_ops,
-                     d_args, d_pause, d_n_ops, max_ops, rec);
+  KIND_SWITCH(q->kind, launch_script<K>(q, lanes, spread, d_ops, d_args, d_pause, d_n_ops,
+                                        max_ops, hist, S(stream)));
   HIP_OK(hipGetLastError());
   return GQ_OK;
 }
@@ -748,14 +867,19 @@ gq_status gq_probe_fence(uint64_t* d_lines, uint32_t lanes, uint32_t iters, uint
   return GQ_OK;
 }
 
+template <int KIND>
+static const void* driver_fn(const char* kernel) {
+  if (!strcmp(kernel, "mix")) return (const void*)k_mix<KIND, false>;
+  if (!strcmp(kernel, "prodcons")) return (const void*)k_prodcons<KIND, false>;
+  return nullptr;
+}
+
 gq_status gq_resident_blocks(const char* kernel, gq_kind kind, uint32_t block,
                              uint32_t* out_blocks) {
   if (!kernel || !out_blocks || block == 0 || block > 1024) return GQ_ERR_INVALID;
-  if (kind != GQ_LFQ) return GQ_ERR_INVALID;
   const void* fn = nullptr;
-  if (!strcmp(kernel, "mix")) fn = (const void*)k_mix<GQ_LFQ, false>;
-  else if (!strcmp(kernel, "prodcons")) fn = (const void*)k_prodcons<GQ_LFQ, false>;
-  else return GQ_ERR_INVALID;
+  KIND_SWITCH(kind, fn = driver_fn<K>(kernel));
+  if (!fn) return GQ_ERR_INVALID;
   return resident_blocks_of(fn, block, out_blocks);
 }
 
@@ -773,4 +897,4 @@ gq_status gq_device_info(uint32_t* cus, uint32_t* wave, char* name, uint32_t len
   return GQ_OK;
 }
 
-}  // extern "C"
+

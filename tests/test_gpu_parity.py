@@ -19,10 +19,11 @@ KINDS = ["lfq"]
 BOUNDED = {"lfq": True, "wfq": True, "ymc": False}
 
 
-def make_queue(kind, n, width=8, lanes=1024, slot_mode="remap"):
+def make_queue(kind, n, width=8, lanes=1024, slot_mode="remap", **opts):
     import paper_2606_01693_amd as gq
-    print(f"[case] kind={kind} n={n} width={width} lanes={lanes} slots={slot_mode}", flush=True)
-    return gq.Queue(kind, n, item_width=width, max_threads=lanes, slot_mode=slot_mode)
+    print(f"[case] kind={kind} n={n} width={width} lanes={lanes} slots={slot_mode} {opts}",
+          flush=True)
+    return gq.Queue(kind, n, item_width=width, max_threads=lanes, slot_mode=slot_mode, **opts)
 
 
 def cap_of(kind, n):
@@ -271,10 +272,10 @@ def test_tiny_histories_linearizable(kind, chunk):
 # ---------------------------------------------------------------------------
 # Mixed 50/50 workload with recorded histories
 # ---------------------------------------------------------------------------
-def run_mix_checked(kind, n, lanes, ops, seed, slot_mode="remap", do_prefill=True):
+def run_mix_checked(kind, n, lanes, ops, seed, slot_mode="remap", do_prefill=True, **opts):
     import paper_2606_01693_amd as gq
     T = torch()
-    q = make_queue(kind, n, lanes=lanes, slot_mode=slot_mode)
+    q = make_queue(kind, n, lanes=lanes, slot_mode=slot_mode, **opts)
     pre = []
     if do_prefill:
         pre = [int(workloads.token(0xFFFFFFFF, i)) for i in range(n // 2)]
@@ -308,6 +309,13 @@ def test_mix_history(kind, n, lanes, ops):
 @pytest.mark.parametrize("kind", KINDS)
 def test_mix_history_padded_slots(kind):
     run_mix_checked(kind, 1 << 10, 16384, 32, workloads.run_seed(2, 77), slot_mode="padded")
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("n", [4, 1 << 10, 1 << 16])
+def test_mix_history_fenced_handoff(kind, n):
+    """The release/acquire payload hand-off (GQ_OPT_FENCED) passes the same checks."""
+    run_mix_checked(kind, n, 16384, 32, workloads.run_seed(2, 78), fenced=True)
 
 
 @pytest.mark.parametrize("kind", KINDS)
