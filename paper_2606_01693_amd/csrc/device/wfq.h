@@ -384,7 +384,11 @@ __device__ __forceinline__ uint64_t run_slow(const WRing& r, uint32_t rid, uint6
                                              uint32_t idx, uint64_t v) {
   uint64_t* G = is_enq ? r.g.tail : r.g.head;
   int64_t* thld = is_enq ? nullptr : r.g.thr;
-  while (slow_faa(r, G, rid, tag, v, thld)) {
+  for (uint32_t rounds = 0; slow_faa(r, G, rid, tag, v, thld); rounds++) {
+    if (rounds >= SPIN_LIMIT) {  // fail-safe: a request never needs this many rounds
+      latch_error(r.err, (uint64_t)(-GQ_ERR_DEVICE));
+      return NO_TICKET;
+    }
     const uint64_t T = l_ctr(v);
     if (is_enq) {
       if (try_enq_slow(r, T, idx, rid, tag)) return T;

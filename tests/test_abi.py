@@ -74,3 +74,26 @@ def test_null_arguments_rejected():
     assert L.gq_create(0, 1024, 8, 1, None, None, 0, None) == b.GQ_ERR_INVALID
     assert L.gq_enqueue_batch(None, None, 0, None, None, None) == b.GQ_ERR_INVALID
     assert L.gq_run_mix(None, 0, 256, 1, None, None, None) == b.GQ_ERR_INVALID
+
+
+def test_wfq_cycle_bound_refused_at_create():
+    """Lemma 4: G-WFQ needs R > D*k/n + 6 (R = 2^15 here)."""
+    from paper_2606_01693_amd import _binding as b
+    # n = 2, D = 64: k = 1023 fits (64*1023 < 32762*2), k = 1024 does not
+    assert b.required_bytes("wfq", 2, 8, 1023) > 0
+    with pytest.raises(b.GQError) as e:
+        b.required_bytes("wfq", 2, 8, 1024)
+    assert e.value.status == b.GQ_ERR_CYCLE_BOUND
+    # a smaller help delay relaxes the bound
+    assert b.required_bytes("wfq", 2, 8, 4000, help_delay=16) > 0
+    # lane ids must fit the 20-bit ThrIdx field
+    with pytest.raises(b.GQError):
+        b.required_bytes("wfq", 1 << 20, 8, 1 << 20)
+
+
+def test_wfq_layout_includes_records():
+    from paper_2606_01693_amd import _binding as b
+    lfq = b.required_bytes("lfq", 1 << 12, 8, 4096)
+    wfq = b.required_bytes("wfq", 1 << 12, 8, 4096)
+    # two rings of 64-byte records per lane plus per-slot owner hints
+    assert wfq - lfq >= 2 * 4096 * 64 + 2 * (2 << 12) * 8

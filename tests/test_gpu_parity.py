@@ -15,7 +15,7 @@ from tests.gpu_util import assert_clean, check_history, drain_fifo, history, tor
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["lfq"]
+KINDS = ["lfq", "wfq"]
 BOUNDED = {"lfq": True, "wfq": True, "ymc": False}
 
 
@@ -59,7 +59,7 @@ def prefill(q, items):
 def test_single_lane_equals_replay(kind, n, seed):
     import paper_2606_01693_amd as gq
     T = torch()
-    q = make_queue(kind, n)
+    q = make_queue(kind, n, lanes=64)
     rng = np.random.default_rng(seed)
     m = 3000
     ops = (rng.random(m) < 0.45).astype(np.uint8)  # 55% enqueues: reaches FULL often
@@ -152,7 +152,7 @@ def test_batch_capacity_exact(kind, n):
     size items."""
     import paper_2606_01693_amd as gq
     T = torch()
-    q = make_queue(kind, n)
+    q = make_queue(kind, n, lanes=512)
     m = n + 100
     items = T.arange(1, m + 1, dtype=T.int64, device="cuda")
     st = T.zeros(m, dtype=T.uint8, device="cuda")
@@ -300,7 +300,7 @@ def run_mix_checked(kind, n, lanes, ops, seed, slot_mode="remap", do_prefill=Tru
 
 
 @pytest.mark.parametrize("kind", KINDS)
-@pytest.mark.parametrize("n,lanes,ops", [(2, 1024, 64), (4, 4096, 32), (64, 16384, 16),
+@pytest.mark.parametrize("n,lanes,ops", [(2, 512, 64), (4, 1536, 32), (64, 16384, 16),
                                          (1 << 10, 16384, 32), (1 << 16, 65536, 16)])
 def test_mix_history(kind, n, lanes, ops):
     run_mix_checked(kind, n, lanes, ops, workloads.run_seed(2, n))
@@ -315,7 +315,8 @@ def test_mix_history_padded_slots(kind):
 @pytest.mark.parametrize("n", [4, 1 << 10, 1 << 16])
 def test_mix_history_fenced_handoff(kind, n):
     """The release/acquire payload hand-off (GQ_OPT_FENCED) passes the same checks."""
-    run_mix_checked(kind, n, 16384, 32, workloads.run_seed(2, 78), fenced=True)
+    lanes = 1024 if n < 64 else 16384  # G-WFQ's cycle bound at tiny capacity
+    run_mix_checked(kind, n, lanes, 32, workloads.run_seed(2, 78), fenced=True)
 
 
 @pytest.mark.parametrize("kind", KINDS)
@@ -323,3 +324,87 @@ def test_mix_full_size(kind):
     """The benchmark's configuration: capacity 2^20, 2048 x 256 lanes, 2^26
     operations, prefill n/2; the full history is checked."""
     run_mix_checked(kind, 1 << 20, 2048 * 256, 128, workloads.run_seed(2, 0))
+
+
+# ---------------------------------------------------------------------------
+# G-WFQ slow path, forced: patience 0 sends every operation through the
+# request/helping path; help delay 1 makes every lane inspect a peer record
+# on every operation.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,lanes,ops,patience,delay", [
+    (4, 256, 16, 0, 1), (64, 1024, 16, 0, 1), (64, 1024, 16, 1, 1), (1 << 10, 4096, 16, 0, 4),
+    (1 << 10, 4096, 16, 2, 64), (16, 2048, 16, 0, 1),
+])
+def test_wfq_forced_slow_path_mix(n, lanes, ops, patience, delay):
+    import paper_2606_01693_amd as gq
+    run_mix_checked("wfq", n, lanes, ops, workloads.run_seed(3, n + patience),
+                    patience=patience, help_delay=delay)
+
+
+@pytest.mark.parametrize("run", range(3))
+def test_wfq_forced_slow_path_role_split(run):
+    import paper_2606_01693_amd as gq
+    T = torch()
+    seed = workloads.run_seed(1, 100 + run)
+    n, lanes, block = 1 << 10, 1024, 256
+    q = make_queue("wfq", n, width=4, lanes=lanes, patience=0, help_delay=1)
+    prod_waves = workloads.producer_waves(seed, 16, 8)
+    role = np.repeat(np.where(prod_waves, 0, 1), 64).astype(np.uint8)
+    counts = T.zeros(4, dtype=T.int64, device="cuda")
+    h = gq.History(lanes, 1 << 14)
+    q.run_prodcons(seed, lanes, block, T.tensor(role, device="cuda"), 16, 8192, 0, 1, counts, h,
+                   max_rounds=1 << 22)
+    T.cuda.synchronize()
+    assert q.check_error() == gq.GQ_OK
+    c = counts.cpu().tolist()
+    assert c[0] == 8192 and c[1] == 8192
+    hist, overflow = history(h)
+    assert overflow == 0
+    drain = drain_fifo(q, n)
+    rep = check_history(hist, drain, capacity=n, token_shift=20)
+    assert_clean(rep, hist, drain, tag=f"wfq_slow_split_{run}")
+    st = q.stats()
+    assert st.slow_enter > 0
+
+
+@pytest.mark.parametrize("chunk", range(2))
+def test_wfq_tiny_histories_slow_path(chunk):
+    """Exhaustive linearizability on tiny runs with every op on the slow path."""
+    import paper_2606_01693_amd as gq
+    T = torch()
+    rng = random.Random(777 + chunk)
+    n = 4
+    q = make_queue("wfq", n, lanes=64, patience=0, help_delay=1)
+    max_ops = 4
+    for trial in range(50):
+        q.reset()
+        pre = [(0xFFFF << 32) | (i + 1) for i in range(rng.randint(0, 2))]
+        prefill(q, pre)
+        lanes = rng.randint(2, 6)
+        ops = np.zeros((lanes, max_ops), dtype=np.uint8)
+        args = np.zeros((lanes, max_ops), dtype=np.uint64)
+        pauses = np.zeros((lanes, max_ops), dtype=np.int16)
+        n_ops = np.array([rng.randint(2, max_ops) for _ in range(lanes)], dtype=np.int32)
+        for g in range(lanes):
+            for r in range(max_ops):
+                ops[g, r] = rng.random() < 0.5
+                args[g, r] = (g << 32) | (r + 1)
+                pauses[g, r] = rng.randint(0, 40)
+        h = gq.History(lanes, max_ops)
+        q.run_script(lanes, True, T.tensor(ops.ravel(), device="cuda"),
+                     T.tensor(args.ravel().view(np.int64), device="cuda"),
+                     T.tensor(pauses.ravel(), device="cuda"),
+                     T.tensor(n_ops, device="cuda"), max_ops, h)
+        T.cuda.synchronize()
+        hist, _ = history(h)
+        drain = drain_fifo(q, n + 4)
+        rows = list(zip(hist.proc.tolist(), hist.op.tolist(), hist.st.tolist(),
+                        hist.val.tolist(), hist.call.tolist(), hist.ret.tolist()))
+        tmax = int(hist.ret.max()) + 10
+        rows += [(99, 1, 0, int(v), tmax + 2 * k, tmax + 2 * k + 1) for k, v in enumerate(drain)]
+        rows += [(99, 1, 1, 0, tmax + 2 * len(drain), tmax + 2 * len(drain) + 1)]
+        ok, _ = oracle.check_linearizable(rows, capacity=n, prefill=pre)
+        assert ok, (trial, rows, pre)
+        rep = check_history(hist, drain, prefill=pre, capacity=n)
+        assert_clean(rep, hist, drain, pre, tag=f"wfq_tiny_slow_{chunk}_{trial}")
+    assert q.check_error() == gq.GQ_OK
