@@ -42,9 +42,11 @@ HBM_PEAK_GBS = 8000.0
 # the kernel sources hash to the value they had when the counters were taken.
 KERNEL_SOURCES = ("paper_2606_01693_amd/csrc/device/common.h",
                   "paper_2606_01693_amd/csrc/device/lfq.h",
+                  "paper_2606_01693_amd/csrc/device/wfq.h",
+                  "paper_2606_01693_amd/csrc/device/ymc.h",
                   "paper_2606_01693_amd/csrc/gq_lib.hip")
-TRAFFIC_PROFILE = {"sources_sha256_16": "f8a143960f840992", "bytes_per_launch": 24.65e9,
-                   "profile": "profiles/k_mix_lfq_cap2p20_ops2p26_fenced.md"}
+TRAFFIC_PROFILE = {}  # kind -> {"sources_sha256_16", "bytes_per_launch", "profile"}
+NAMES = {"lfq": "G-LFQ", "wfq": "G-WFQ", "ymc": "G-WFQ-YMC"}
 
 
 def kernel_sources_hash() -> str:
@@ -133,7 +135,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--kind", default="lfq", choices=["lfq"])
+    ap.add_argument("--kinds", default="lfq,wfq,ymc",
+                    help="comma-separated queue variants run by each step")
     ap.add_argument("--slot-mode", default="remap", choices=["remap", "padded"])
     ap.add_argument("--fenced", action="store_true",
                     help="release/acquire payload hand-off instead of the atomic exchange")
@@ -152,47 +155,74 @@ def main():
     torch.cuda.set_device(0)
     info = gq.device_info()
     log(f"[bench] device {info}")
-    q = gq.Queue(args.kind, CAP, item_width=ITEM_BYTES, max_threads=LANES,
-                 slot_mode=args.slot_mode, fenced=args.fenced)
-    pre = torch.arange(1, CAP // 2 + 1, dtype=torch.int64, device="cuda") | (0xFFFFFFFF << 32)
-    q.enqueue_batch(pre)
-    counts = torch.zeros(4, dtype=torch.int64, device="cuda")
+    kinds = [k for k in args.kinds.split(",") if k]
     base_seed = workloads.run_seed(2, 0)
+    queues, counts = {}, {}
+    for kind in kinds:
+        # G-WFQ-YMC's pool must cover every ticket of the run (no reset
+        # between steps): 2^29 cells of 32 B.
+        q = gq.Queue(kind, CAP, item_width=ITEM_BYTES, max_threads=LANES,
+                     slot_mode=args.slot_mode, fenced=args.fenced,
+                     ymc_pool_cells=(1 << 29) if kind == "ymc" else 0)
+        pre = torch.arange(1, CAP // 2 + 1, dtype=torch.int64, device="cuda") | (0xFFFFFFFF << 32)
+        q.enqueue_batch(pre)
+        queues[kind] = q
+        counts[kind] = torch.zeros(4, dtype=torch.int64, device="cuda")
     step = 0
     for _ in range(args.warmup):
-        q.run_mix(base_seed + step, LANES, OPS_PER_LANE, counts)
+        for kind in kinds:
+            queues[kind].run_mix(base_seed + step, LANES, OPS_PER_LANE, counts[kind])
         step += 1
     torch.cuda.synchronize()
-    assert q.check_error() == gq.GQ_OK
-    counts.zero_()
-    events = []
+    for kind in kinds:
+        assert queues[kind].check_error() == gq.GQ_OK, kind
+        counts[kind].zero_()
+        queues[kind].clear_stats()
+    events = {k: [] for k in kinds}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        q.run_mix(base_seed + step, LANES, OPS_PER_LANE, counts)
-        e1.record()
-        events.append((e0, e1))
+        for kind in kinds:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            queues[kind].run_mix(base_seed + step, LANES, OPS_PER_LANE, counts[kind])
+            e1.record()
+            events[kind].append((e0, e1))
         step += 1
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    err = q.check_error()
-    if err != gq.GQ_OK:
-        raise SystemExit(f"device error {gq.status_str(err)}")
-    c = counts.cpu().tolist()
-    ok_ops = c[0] + c[1]
     wall = t1 - t0
-    kernel_ms = [a.elapsed_time(b) for a, b in events]
-    kavg = float(np.mean(kernel_ms))
-    value = ok_ops / wall / 1e6
-    per_launch_ok = ok_ops / args.steps
-    achieved_gbs = per_launch_ok * BYTES_PER_OP / (kavg * 1e-3) / 1e9
-    log(f"[bench] counts ok_enq={c[0]} ok_deq={c[1]} full={c[2]} empty={c[3]} "
-        f"kernel_ms={kernel_ms}")
-    stats = q.stats()
-
+    variants = {}
+    ok_total = 0
+    for kind in kinds:
+        err = queues[kind].check_error()
+        if err != gq.GQ_OK:
+            raise SystemExit(f"device error on {kind}: {gq.status_str(err)}")
+        c = counts[kind].cpu().tolist()
+        ok = c[0] + c[1]
+        ok_total += ok
+        kms = [a.elapsed_time(b) for a, b in events[kind]]
+        kavg = float(np.mean(kms))
+        per_launch_ok = ok / args.steps
+        st = queues[kind].stats()
+        variants[kind] = {
+            "name": NAMES[kind],
+            "mops": per_launch_ok / (kavg * 1e-3) / 1e6,
+            "kernel_ms_avg": kavg,
+            "ok_ops_per_step": per_launch_ok,
+            "full_per_step": c[2] / args.steps,
+            "empty_per_step": c[3] / args.steps,
+            "cas_fail_per_ok_op": st.cas_fail / max(1, ok),
+            "slow_path_entries_per_step": st.slow_enter / args.steps,
+            "helps_per_step": st.helps / args.steps,
+        }
+        log(f"[bench] {kind}: counts {c} kernel_ms={kms}")
+    value = ok_total / wall / 1e6
+    dom = max(kinds, key=lambda k: variants[k]["kernel_ms_avg"])
+    dv = variants[dom]
+    achieved_gbs = dv["ok_ops_per_step"] * BYTES_PER_OP / (dv["kernel_ms_avg"] * 1e-3) / 1e9
+    traffic = TRAFFIC_PROFILE.get(dom)
     out = {
         "metric": "Mops/s enq+deq at 50/50 mix, 2^20-slot queue",
         "value": value,
@@ -207,27 +237,25 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {
-            "workload": f"G-LFQ ({args.kind}) mixed 50/50, capacity 2^20, uint64 payload, "
-                        f"2^26 op attempts per step, 2048 WGs x 256 lanes, prefill n/2, "
-                        f"slots={args.slot_mode}, hand-off={'fenced' if args.fenced else 'atomic'}",
+            "workload": "mixed 50/50 enqueue/dequeue, capacity 2^20, uint64 payload, 2^26 op "
+                        "attempts per queue per step by 2048 WGs x 256 lanes, prefill n/2; one "
+                        "step runs that batch through each queue variant in turn: "
+                        + ", ".join(NAMES[k] for k in kinds)
+                        + f"; slots={args.slot_mode}, hand-off="
+                        + ("fenced" if args.fenced else "atomic"),
             "capacity": CAP, "lanes": LANES, "ops_per_lane": OPS_PER_LANE,
-            "parallelism": "single GPU",
+            "variants": kinds, "parallelism": "single GPU",
         },
-        "kernel_ms_avg": kavg,
-        "ok_ops_per_step": per_launch_ok,
-        "full_per_step": c[2] / args.steps,
-        "empty_per_step": c[3] / args.steps,
-        "cas_fail_per_ok_op": stats.cas_fail / max(1, stats.ok_enq + stats.ok_deq + ok_ops),
+        "variants": variants,
         "roofline": {
             "bound": "hbm",
             "achieved": achieved_gbs,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": (TRAFFIC_PROFILE["bytes_per_launch"]
-                        if kernel_sources_hash() == TRAFFIC_PROFILE["sources_sha256_16"]
-                        else None),
-            "kernel": "k_mix<G-LFQ>",
+            "traffic": (traffic["bytes_per_launch"] if traffic and
+                        kernel_sources_hash() == traffic["sources_sha256_16"] else None),
+            "kernel": f"k_mix<{NAMES[dom]}>",
             "bytes_per_ok_op": BYTES_PER_OP,
         },
     }
@@ -241,15 +269,16 @@ def main():
         bound_ops = min(2 * a * p["r_ctr_wave_faa_per_s"],
                         p["r_slot_cas_per_s"] / 2.0,
                         p["hbm_copy_gbs"] * 1e9 / BYTES_PER_OP)
-        out["atomic_roofline"] = dict(p, bound_mops=bound_ops / 1e6,
-                                      frac=(per_launch_ok / (kavg * 1e-3)) / bound_ops)
+        out["atomic_roofline"] = dict(p, bound_mops=bound_ops / 1e6, kernel=NAMES[dom],
+                                      frac=dv["mops"] * 1e6 / bound_ops)
     if not args.no_cpu:
-        replay, locked = cpu_baselines(base_seed, 1 << 17)
+        replay, locked = cpu_baselines(base_seed, LANES)
         out["cpu_baseline"] = replay
         out["cpu_locked_queue"] = locked
         out["host"] = {"cpu": platform.processor() or platform.machine(),
                        "cores": os.cpu_count()}
-    q.close()
+    for q in queues.values():
+        q.close()
     print(json.dumps(out), flush=True)
 
 

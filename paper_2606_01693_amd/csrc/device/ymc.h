@@ -1,16 +1,303 @@
-// G-WFQ-YMC (Section III-A): placeholder until the slow path lands; gq_create
-// refuses GQ_WFQ_YMC while this header only declares the interface.
+// G-WFQ-YMC: the Yang / Mellor-Crummey wait-free queue adapted to the GPU
+// (Section III-A).
+//
+// An unbounded array of cells {val, enq, deq} indexed by two monotone
+// counters T and H.  Fast path: an enqueue takes a cell with FAA(T) and CASes
+// its value in; a dequeue takes a cell with FAA(H) and claims the value there.
+// After `patience` failures an operation publishes a per-lane request that
+// other lanes complete: dequeuers help pending enqueue requests of peers on
+// the cells they visit, and every successful dequeue helps one peer's pending
+// dequeue request.  The queue logic, helping structure and linearization
+// points follow the original algorithm.
+//
+// GPU adaptation (Section III-A): the linked segments and their hazard-
+// pointer reclamation are replaced by one preallocated pool with direct
+// arithmetic lookup, cell(i) = pool + i; running past the pool latches
+// GQ_ERR_POOL_EXHAUSTED.  Request "pointers" in cells are lane ids + 1 (0 is
+// the empty marker, all ones the taken marker); request states pack
+// <pending:1 | id:63> into one 64-bit word.  Tickets come from the wave-
+// aggregated fetch-and-add, which yields the same ticket order as per-lane
+// FAA (Lemma 1).
+//
+// Values: a cell stores item + 1, so 0 can mark an empty cell, all ones an
+// unusable one and all ones - 1 the internal "empty" result; 8-byte queues
+// therefore reject the items 2^64 - 3 .. 2^64 - 1 (GQ_ERR_INVALID).
+// G-WFQ-YMC is unbounded within its pool and never answers FULL.
 #pragma once
 #include "common.h"
+
 namespace gq {
 namespace ymc {
-__device__ __forceinline__ int enqueue(const gq_dev& q, uint64_t, uint32_t, uint32_t&) {
-  latch_error(q.err, (uint64_t)(-GQ_ERR_INVALID));
-  return GQ_ERR_INVALID;
+
+constexpr uint64_t BOT = 0;               // empty cell value / no request
+constexpr uint64_t TOP = ~0ull;           // unusable cell value / taken
+constexpr uint64_t PENDING = 1ull << 63;
+constexpr uint64_t ID_MASK = PENDING - 1;
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+constexpr uint64_t RES_EMPTY = TOP - 1;   // internal: "queue was empty"
+
+struct Cell {
+  uint64_t val;
+  uint64_t enq;   // 0, lane + 1 of the enqueue request reserved here, or TOP
+  uint64_t deq;   // 0, lane + 1 of the dequeue request served here, or TOP
+  uint64_t pad;
+};
+
+struct Handle {          // one per lane, 64 bytes
+  uint64_t enq_val;      // enqueue request: value (stored form)
+  uint64_t enq_state;    // <pending | id>: id = first cell tried, then the claimed cell
+  uint64_t deq_id;       // dequeue request: id = first cell tried
+  uint64_t deq_state;    // <pending | idx>: idx = announced candidate cell
+  uint64_t enq_help_id;  // private: remembered id of the enqueue request being helped
+  uint32_t enq_peer;     // private: next lane whose enqueue request to look at
+  uint32_t deq_peer;     // private: next lane whose dequeue request to help
+  uint64_t pad[3];
+};
+
+struct Q {
+  Cell* pool;
+  uint64_t cells;
+  uint64_t* T;
+  uint64_t* H;
+  Handle* hd;
+  uint32_t k;
+  uint32_t patience_enq, patience_deq;
+  uint64_t* err;
+  uint64_t* stats;
+};
+
+__device__ __forceinline__ Q make_q(const gq_dev& q) {
+  Q y;
+  y.pool = (Cell*)q.ymc_cells;
+  y.cells = q.ymc_pool_cells;
+  y.T = q.ymc_ctr;
+  y.H = q.ymc_ctr + 32;
+  y.hd = (Handle*)q.ymc_handles;
+  y.k = q.max_threads;
+  y.patience_enq = q.patience_enq;
+  y.patience_deq = q.patience_deq;
+  y.err = q.err;
+  y.stats = q.stats;
+  return y;
 }
-__device__ __forceinline__ int dequeue(const gq_dev& q, uint64_t*, uint32_t, uint32_t&) {
-  latch_error(q.err, (uint64_t)(-GQ_ERR_INVALID));
-  return GQ_ERR_INVALID;
+
+// Cell lookup into the preallocated pool; NULL (and a latched error) when the
+// pool is exhausted.
+__device__ __forceinline__ Cell* cell(const Q& y, uint64_t i) {
+  if (i >= y.cells) {
+    latch_error(y.err, (uint64_t)(-GQ_ERR_POOL_EXHAUSTED));
+    return nullptr;
+  }
+  return y.pool + i;
 }
+
+__device__ __forceinline__ void advance_end(uint64_t* E, uint64_t v) {
+  uint64_t e = ld(E);
+  while (e < v)
+    if (cas(E, e, v)) break;
+}
+
+__device__ __forceinline__ bool try_claim(uint64_t* state, uint64_t id, uint64_t cell_id) {
+  uint64_t e = PENDING | id;
+  return cas_acqrel(state, e, cell_id);
+}
+
+__device__ __forceinline__ void enq_commit(const Q& y, Cell* c, uint64_t v, uint64_t cid) {
+  advance_end(y.T, cid + 1);
+  st(&c->val, v);
+}
+
+// help_enq: make cell i decided for dequeuers.  Returns the cell's value, TOP
+// (no value will come to this cell), or RES_EMPTY (the queue was empty).
+// The cell's own words carry the value, so the cell CASes of the fast paths
+// are relaxed; request records (value, then state) are published with
+// release and read with acquire.
+__device__ __forceinline__ uint64_t help_enq(const Q& y, Handle* h, Cell* c, uint64_t i) {
+  uint64_t e = BOT;
+  if (!cas(&c->val, e, TOP) && e != TOP) return e;
+  // c->val is TOP: help a pending slow-path enqueue use this cell
+  if (ld_acq(&c->enq) == BOT) {
+    uint32_t p = 0;
+    uint64_t s = 0;
+    for (uint32_t spin = 0;; spin++) {
+      p = h->enq_peer;
+      if (p >= y.k) p = 0;
+      s = ld_acq(&y.hd[p].enq_state);
+      if (h->enq_help_id == 0 || h->enq_help_id == (s & ID_MASK) || spin >= y.k) break;
+      h->enq_help_id = 0;
+      h->enq_peer = p + 1 >= y.k ? 0 : p + 1;
+    }
+    uint64_t ee = BOT;
+    if ((s & PENDING) && (s & ID_MASK) <= i && !cas_acqrel(&c->enq, ee, (uint64_t)p + 1)) {
+      h->enq_help_id = s & ID_MASK;  // could not reserve: retry this request next time
+    } else {
+      h->enq_peer = p + 1 >= y.k ? 0 : p + 1;
+    }
+    ee = BOT;
+    if (ld_acq(&c->enq) == BOT) cas_acqrel(&c->enq, ee, TOP);
+  }
+  const uint64_t ce = ld_acq(&c->enq);
+  if (ce == TOP) return ld(y.T) <= i ? RES_EMPTY : TOP;
+  Handle* r = &y.hd[ce - 1];
+  const uint64_t s = ld_acq(&r->enq_state);
+  const uint64_t v = ld_acq(&r->enq_val);
+  if ((s & ID_MASK) > i) {
+    // the request started after this cell: it cannot use it
+    if (ld(&c->val) == TOP && ld(y.T) <= i) return RES_EMPTY;
+  } else if (try_claim(&r->enq_state, s & ID_MASK, i) || (s == i && ld(&c->val) == TOP)) {
+    enq_commit(y, c, v, i);
+  }
+  return ld_acq(&c->val);
+}
+
+// ---- enqueue -------------------------------------------------------------------
+__device__ __forceinline__ bool enq_fast(const Q& y, uint64_t v, uint64_t& id) {
+  const uint64_t i = wave_faa(y.T, 1);
+  Cell* c = cell(y, i);
+  if (!c) return true;  // pool exhausted: error latched, give up
+  uint64_t e = BOT;
+  if (cas(&c->val, e, v)) return true;
+  id = i;
+  return false;
+}
+
+__device__ __forceinline__ void enq_slow(const Q& y, uint32_t tid, uint64_t v, uint64_t cell_id) {
+  Handle* me = &y.hd[tid];
+  st(&me->enq_val, v);
+  st_rel(&me->enq_state, PENDING | cell_id);
+  for (uint32_t spin = 0;; spin++) {
+    if (spin >= SPIN_LIMIT) { latch_error(y.err, (uint64_t)(-GQ_ERR_DEVICE)); return; }
+    const uint64_t i = wave_faa(y.T, 1);
+    Cell* c = cell(y, i);
+    if (!c) return;
+    uint64_t e = BOT;
+    if (cas_acqrel(&c->enq, e, (uint64_t)tid + 1) && ld(&c->val) == BOT) {
+      try_claim(&me->enq_state, cell_id, i);
+      break;
+    }
+    if (!(ld_acq(&me->enq_state) & PENDING)) break;
+  }
+  const uint64_t id = ld_acq(&me->enq_state) & ID_MASK;
+  Cell* c = cell(y, id);
+  if (c) enq_commit(y, c, v, id);
+}
+
+__device__ __forceinline__ int enqueue(const gq_dev& q, uint64_t item, uint32_t tid, uint32_t& cf) {
+  const Q y = make_q(q);
+  if (tid >= y.k || (q.item_width == 8 && item >= RES_EMPTY - 1)) {
+    latch_error(q.err, (uint64_t)(-GQ_ERR_INVALID));
+    return GQ_ERR_INVALID;
+  }
+  const uint64_t v = (q.item_width == 8 ? item : (item & 0xFFFFFFFFull)) + 1;
+  uint64_t id = 0;
+  // At least one fast attempt: the slow path starts from the cell that
+  // attempt took (patience 0 means "one attempt, then the slow path").
+  const uint32_t pat = y.patience_enq ? y.patience_enq : 1;
+  for (uint32_t p = 0; p < pat; p++) {
+    if (enq_fast(y, v, id)) return ld(y.err) ? GQ_ERR_POOL_EXHAUSTED : GQ_OK;
+    cf++;
+  }
+  faa(y.stats + S_SLOW, 1ull);
+  enq_slow(y, tid, v, id);
+  return GQ_OK;
+}
+
+// ---- dequeue -------------------------------------------------------------------
+__device__ void help_deq(const Q& y, Handle* h, uint32_t helpee) {
+  Handle* r = &y.hd[helpee];
+  uint64_t s = ld_acq(&r->deq_state);
+  const uint64_t id = ld_acq(&r->deq_id);
+  if (!(s & PENDING) || (s & ID_MASK) < id) return;
+  uint64_t prior = id, i = id, cand = 0;
+  for (uint32_t spin = 0;; spin++) {
+    if (spin >= SPIN_LIMIT) { latch_error(y.err, (uint64_t)(-GQ_ERR_DEVICE)); return; }
+    // look for a candidate cell until one is found or another helper announces one
+    for (uint32_t walk = 0; !cand && (s & ID_MASK) == prior; walk++) {
+      if (walk >= SPIN_LIMIT) { latch_error(y.err, (uint64_t)(-GQ_ERR_DEVICE)); return; }
+      Cell* c = cell(y, ++i);
+      if (!c) return;
+      const uint64_t v = help_enq(y, h, c, i);
+      if (v == RES_EMPTY || (v != TOP && ld_acq(&c->deq) == BOT)) cand = i;
+      else s = ld_acq(&r->deq_state);
+    }
+    if (cand) {
+      uint64_t e = PENDING | prior;
+      cas_acqrel(&r->deq_state, e, PENDING | cand);
+      s = ld_acq(&r->deq_state);
+    }
+    if (!(s & PENDING) || ld_acq(&r->deq_id) != id) return;
+    Cell* c = cell(y, s & ID_MASK);
+    if (!c) return;
+    uint64_t d = BOT;
+    if (ld_acq(&c->val) == TOP || cas_acqrel(&c->deq, d, (uint64_t)helpee + 1) ||
+        d == (uint64_t)helpee + 1) {
+      uint64_t e = s;
+      cas_acqrel(&r->deq_state, e, s & ID_MASK);
+      return;
+    }
+    prior = s & ID_MASK;
+    if ((s & ID_MASK) >= i) {
+      cand = 0;
+      i = s & ID_MASK;
+    }
+  }
+}
+
+// deq_fast: returns a stored value, RES_EMPTY, or TOP (try again / go slow).
+__device__ __forceinline__ uint64_t deq_fast(const Q& y, Handle* h, uint64_t& id) {
+  const uint64_t i = wave_faa(y.H, 1);
+  Cell* c = cell(y, i);
+  if (!c) return RES_EMPTY;
+  const uint64_t v = help_enq(y, h, c, i);
+  if (v == RES_EMPTY) return RES_EMPTY;
+  uint64_t d = BOT;
+  if (v != TOP && cas(&c->deq, d, TOP)) return v;
+  id = i;
+  return TOP;
+}
+
+__device__ __forceinline__ uint64_t deq_slow(const Q& y, uint32_t tid, uint64_t cid) {
+  Handle* me = &y.hd[tid];
+  st(&me->deq_id, cid);
+  st_rel(&me->deq_state, PENDING | cid);
+  help_deq(y, me, tid);
+  const uint64_t i = ld_acq(&me->deq_state) & ID_MASK;
+  Cell* c = cell(y, i);
+  if (!c) return RES_EMPTY;
+  const uint64_t v = ld_acq(&c->val);
+  advance_end(y.H, i + 1);
+  return v == TOP ? RES_EMPTY : v;
+}
+
+__device__ __forceinline__ int dequeue(const gq_dev& q, uint64_t* item, uint32_t tid, uint32_t& cf) {
+  const Q y = make_q(q);
+  if (tid >= y.k) {
+    latch_error(q.err, (uint64_t)(-GQ_ERR_INVALID));
+    return GQ_ERR_INVALID;
+  }
+  Handle* me = &y.hd[tid];
+  uint64_t v = TOP, id = 0;
+  // At least one fast attempt: every cell a dequeuer takes from H must be
+  // visited, and the slow path walks forward from the cell of the last one.
+  const uint32_t pat = y.patience_deq ? y.patience_deq : 1;
+  for (uint32_t p = 0; p < pat; p++) {
+    v = deq_fast(y, me, id);
+    if (v != TOP) break;
+    cf++;
+  }
+  if (v == TOP) {
+    faa(y.stats + S_SLOW, 1ull);
+    v = deq_slow(y, tid, id);
+  }
+  if (v == RES_EMPTY) return ld(y.err) ? GQ_ERR_POOL_EXHAUSTED : GQ_EMPTY;
+  // a successful dequeue helps one peer's pending dequeue request
+  uint32_t p = me->deq_peer;
+  if (p >= y.k) p = 0;
+  if (p != tid) help_deq(y, me, p);
+  me->deq_peer = p + 1 >= y.k ? 0 : p + 1;
+  *item = v - 1;
+  return GQ_OK;
+}
+
 }  // namespace ymc
 }  // namespace gq

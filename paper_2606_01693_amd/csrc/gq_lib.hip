@@ -69,7 +69,14 @@ struct Layout {
   uint64_t slots_aq, slots_fq, data, rec_aq, rec_fq, own_aq, own_fq, ymc_pool, ymc_handles, total;
 };
 
-bool kind_supported(gq_kind kind) { return kind == GQ_LFQ || kind == GQ_WFQ; }
+bool kind_supported(gq_kind kind) {
+  return kind == GQ_LFQ || kind == GQ_WFQ || kind == GQ_WFQ_YMC;
+}
+
+uint64_t ymc_default_cells(uint64_t n) {
+  const uint64_t c = 64 * n;
+  return c > (1ull << 20) ? c : (1ull << 20);
+}
 
 // G-WFQ: Lemma 4 requires R > D*k/n + 6 for the cycle range R of its tags.
 bool wfq_cycle_bound_ok(uint64_t n, uint64_t k, uint64_t D) {
@@ -111,6 +118,15 @@ gq_status plan(gq_kind kind, uint64_t n, uint32_t w, uint32_t k, const gq_option
     off = align_up(off + 2 * n * 8, 4096);
     L->own_fq = off;
     off = align_up(off + 2 * n * 8, 4096);
+  }
+  if (kind == GQ_WFQ_YMC) {
+    const uint64_t cells = (o && o->ymc_pool_cells) ? o->ymc_pool_cells : ymc_default_cells(n);
+    if (cells < 2 || cells > (1ull << 34)) return GQ_ERR_INVALID;
+    if (k >= (1u << 31)) return GQ_ERR_INVALID;
+    L->ymc_pool = off;
+    off = align_up(off + cells * sizeof(ymc::Cell), 4096);
+    L->ymc_handles = off;
+    off = align_up(off + (uint64_t)k * sizeof(ymc::Handle), 4096);
   }
   L->total = off;
   return GQ_OK;
@@ -178,6 +194,36 @@ __global__ void k_init_wfq(gq_dev q) {
     st(q.fq.head, 0ull);
     st(q.fq.tail, q.capacity << wfq::TID_BITS);
     st(q.fq.threshold, lfq::threshold_reset(q));
+    st(q.err, 0ull);
+    for (int s = 0; s < S_NUM; s++) st(q.stats + s, 0ull);
+  }
+}
+
+// G-WFQ-YMC: every cell empty {0, 0, 0}, T = H = 1 (cell id 0 doubles as
+// "no id"), handles cleared with peers staggered by lane.
+__global__ void k_init_ymc(gq_dev q) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t g0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  ymc::Cell* pool = (ymc::Cell*)q.ymc_cells;
+  for (uint64_t i = g0; i < q.ymc_pool_cells; i += stride) {
+    st(&pool[i].val, 0ull);
+    st(&pool[i].enq, 0ull);
+    st(&pool[i].deq, 0ull);
+  }
+  ymc::Handle* hd = (ymc::Handle*)q.ymc_handles;
+  for (uint64_t t = g0; t < q.max_threads; t += stride) {
+    st(&hd[t].enq_val, 0ull);
+    st(&hd[t].enq_state, 0ull);
+    st(&hd[t].deq_id, 0ull);
+    st(&hd[t].deq_state, 0ull);
+    st(&hd[t].enq_help_id, 0ull);
+    const uint32_t peer = (uint32_t)((t + 1) % q.max_threads);
+    hd[t].enq_peer = peer;
+    hd[t].deq_peer = peer;
+  }
+  if (g0 == 0) {
+    st(q.ymc_ctr, 1ull);
+    st(q.ymc_ctr + 32, 1ull);
     st(q.err, 0ull);
     for (int s = 0; s < S_NUM; s++) st(q.stats + s, 0ull);
   }
@@ -468,6 +514,9 @@ static gq_status launch_init(gq_queue* q, hipStream_t s) {
     case GQ_WFQ:
       LAUNCH(k_init_wfq, dim3(grid), dim3(kBlock), 0, s, q->dev);
       break;
+    case GQ_WFQ_YMC:
+      LAUNCH(k_init_ymc, dim3(8192), dim3(kBlock), 0, s, q->dev);
+      break;
     default:
       return GQ_ERR_INVALID;
   }
@@ -588,6 +637,17 @@ gq_status gq_create(gq_kind kind, uint64_t capacity, uint32_t item_width, uint32
   d.fq.head = (uint64_t*)(q->buf + OFF_FQ_HEAD);
   d.fq.tail = (uint64_t*)(q->buf + OFF_FQ_TAIL);
   d.fq.threshold = (int64_t*)(q->buf + OFF_FQ_THR);
+  if (kind == GQ_WFQ_YMC) {
+    d.ymc_cells = (uint64_t*)(q->buf + L.ymc_pool);
+    d.ymc_pool_cells = (q->opt.ymc_pool_cells ? q->opt.ymc_pool_cells : ymc_default_cells(capacity));
+    d.ymc_handles = q->buf + L.ymc_handles;
+    d.patience_enq = 10;  // the original algorithm's PATIENCE
+    d.patience_deq = 10;
+    if (q->opt.flags & GQ_OPT_WFQ_TUNING) {
+      d.patience_enq = q->opt.wfq_patience_enq;
+      d.patience_deq = q->opt.wfq_patience_deq;
+    }
+  }
   if (kind == GQ_WFQ) {
     d.aq.records = q->buf + L.rec_aq;
     d.fq.records = q->buf + L.rec_fq;
@@ -630,6 +690,7 @@ gq_status gq_enqueue_batch(gq_queue* q, const void* d_items, uint64_t m, uint8_t
   switch (q->kind) {
     case GQ_LFQ: launch_enq<GQ_LFQ>(q, d_items, m, d_status, d_num_ok, S(stream)); break;
     case GQ_WFQ: launch_enq<GQ_WFQ>(q, d_items, m, d_status, d_num_ok, S(stream)); break;
+    case GQ_WFQ_YMC: launch_enq<GQ_WFQ_YMC>(q, d_items, m, d_status, d_num_ok, S(stream)); break;
     default: return GQ_ERR_INVALID;
   }
   HIP_OK(hipGetLastError());
@@ -643,6 +704,7 @@ gq_status gq_dequeue_batch(gq_queue* q, void* d_out, uint64_t m, uint8_t* d_stat
   switch (q->kind) {
     case GQ_LFQ: launch_deq<GQ_LFQ>(q, d_out, m, d_status, d_num_ok, S(stream)); break;
     case GQ_WFQ: launch_deq<GQ_WFQ>(q, d_out, m, d_status, d_num_ok, S(stream)); break;
+    case GQ_WFQ_YMC: launch_deq<GQ_WFQ_YMC>(q, d_out, m, d_status, d_num_ok, S(stream)); break;
     default: return GQ_ERR_INVALID;
   }
   HIP_OK(hipGetLastError());
@@ -704,6 +766,7 @@ static Rec make_rec(const gq_history* h) {
   switch (kind) {                                    \
     case GQ_LFQ: { constexpr int K = GQ_LFQ; CALL; } break; \
     case GQ_WFQ: { constexpr int K = GQ_WFQ; CALL; } break; \
+    case GQ_WFQ_YMC: { constexpr int K = GQ_WFQ_YMC; CALL; } break; \
     default: return GQ_ERR_INVALID;                  \
   }
 

@@ -15,7 +15,7 @@ from tests.gpu_util import assert_clean, check_history, drain_fifo, history, tor
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["lfq", "wfq"]
+KINDS = ["lfq", "wfq", "ymc"]
 BOUNDED = {"lfq": True, "wfq": True, "ymc": False}
 
 
@@ -255,7 +255,7 @@ def test_tiny_histories_linearizable(kind, chunk):
                      T.tensor(n_ops, device="cuda"), max_ops, h)
         T.cuda.synchronize()
         hist, _ = history(h)
-        drain = drain_fifo(q, n + 4)
+        drain = drain_fifo(q, n + 4 if BOUNDED[kind] else 64)
         rows = list(zip(hist.proc.tolist(), hist.op.tolist(), hist.st.tolist(),
                         hist.val.tolist(), hist.call.tolist(), hist.ret.tolist()))
         tmax = int(hist.ret.max()) + 10
@@ -408,3 +408,77 @@ def test_wfq_tiny_histories_slow_path(chunk):
         rep = check_history(hist, drain, prefill=pre, capacity=n)
         assert_clean(rep, hist, drain, pre, tag=f"wfq_tiny_slow_{chunk}_{trial}")
     assert q.check_error() == gq.GQ_OK
+
+
+# ---------------------------------------------------------------------------
+# G-WFQ-YMC slow path, forced (patience 0), and the pool-exhaustion latch.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,lanes,ops,patience", [(64, 1024, 16, 0), (1 << 10, 4096, 16, 1),
+                                                   (16, 2048, 16, 0)])
+def test_ymc_forced_slow_path_mix(n, lanes, ops, patience):
+    run_mix_checked("ymc", n, lanes, ops, workloads.run_seed(4, n + patience), patience=patience)
+
+
+@pytest.mark.parametrize("run", range(2))
+def test_ymc_forced_slow_path_role_split(run):
+    import paper_2606_01693_amd as gq
+    T = torch()
+    seed = workloads.run_seed(1, 200 + run)
+    n, lanes, block = 1 << 10, 1024, 256
+    q = make_queue("ymc", n, width=4, lanes=lanes, patience=0)
+    prod_waves = workloads.producer_waves(seed, 16, 8)
+    role = np.repeat(np.where(prod_waves, 0, 1), 64).astype(np.uint8)
+    counts = T.zeros(4, dtype=T.int64, device="cuda")
+    h = gq.History(lanes, 1 << 14)
+    q.run_prodcons(seed, lanes, block, T.tensor(role, device="cuda"), 16, 8192, 0, 1, counts, h,
+                   max_rounds=1 << 22)
+    T.cuda.synchronize()
+    assert q.check_error() == gq.GQ_OK
+    c = counts.cpu().tolist()
+    assert c[0] == 8192 and c[1] == 8192
+    hist, overflow = history(h)
+    assert overflow == 0
+    drain = drain_fifo(q, 64)
+    rep = check_history(hist, drain, capacity=0, token_shift=20)
+    assert_clean(rep, hist, drain, tag=f"ymc_slow_split_{run}")
+
+
+@pytest.mark.parametrize("patience", [0, 2])
+def test_ymc_slow_enqueue_after_empty_burst(patience):
+    """Dequeuers that found the queue empty leave their cells unusable; the
+    enqueues that follow land on those cells, fail their fast attempts and
+    complete on the slow path.  Every item must still come out, in batches'
+    order."""
+    import paper_2606_01693_amd as gq
+    T = torch()
+    q = make_queue("ymc", 1 << 10, lanes=4096, patience=patience)
+    out = T.zeros(4096, dtype=T.int64, device="cuda")
+    st = T.zeros(4096, dtype=T.uint8, device="cuda")
+    q.dequeue_batch(out, st)              # 4096 EMPTY: H runs ahead of T
+    items = T.arange(1, 3001, dtype=T.int64, device="cuda")
+    st_e = T.zeros(3000, dtype=T.uint8, device="cuda")
+    q.enqueue_batch(items, st_e)
+    out2 = T.zeros(3000, dtype=T.int64, device="cuda")
+    st2 = T.zeros(3000, dtype=T.uint8, device="cuda")
+    q.dequeue_batch(out2, st2)
+    T.cuda.synchronize()
+    assert q.check_error() == gq.GQ_OK
+    assert (st.cpu().numpy() == gq.GQ_EMPTY).all()
+    assert (st_e.cpu().numpy() == gq.GQ_OK).all()
+    assert (st2.cpu().numpy() == gq.GQ_OK).all()
+    assert sorted(out2.cpu().tolist()) == list(range(1, 3001))
+    assert q.stats().slow_enter > 0
+
+
+def test_ymc_pool_exhaustion_latches():
+    """Running past the preallocated pool reports GQ_ERR_POOL_EXHAUSTED."""
+    import paper_2606_01693_amd as gq
+    T = torch()
+    q = gq.Queue("ymc", 64, item_width=8, max_threads=256, ymc_pool_cells=512)
+    items = T.arange(1, 1001, dtype=T.int64, device="cuda")
+    st = T.zeros(1000, dtype=T.uint8, device="cuda")
+    q.enqueue_batch(items, st)
+    T.cuda.synchronize()
+    assert q.check_error() == gq.GQ_ERR_POOL_EXHAUSTED
+    s = st.cpu().numpy().astype(np.int8)
+    assert (s == gq.GQ_OK).sum() <= 512
