@@ -137,7 +137,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--kinds", default="lfq,wfq,ymc",
                     help="comma-separated queue variants run by each step")
-    ap.add_argument("--slot-mode", default="remap", choices=["remap", "padded"])
+    ap.add_argument("--slot-mode", default="linear", choices=["remap", "padded", "linear"])
     ap.add_argument("--fenced", action="store_true",
                     help="release/acquire payload hand-off instead of the atomic exchange")
     ap.add_argument("--no-cpu", action="store_true")

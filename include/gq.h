@@ -56,8 +56,11 @@ typedef enum { GQ_LFQ = 0, GQ_WFQ = 1, GQ_WFQ_YMC = 2 } gq_kind;
  * line to avoid false sharing, Section V "Devices"):
  *   GQ_SLOTS_REMAP   8-byte entries, 16 per 128-byte line, with consecutive
  *                    tickets mapped to different lines (compact footprint);
- *   GQ_SLOTS_PADDED  one entry per 128-byte line.                            */
-typedef enum { GQ_SLOTS_REMAP = 0, GQ_SLOTS_PADDED = 1 } gq_slot_mode;
+ *   GQ_SLOTS_PADDED  one entry per 128-byte line;
+ *   GQ_SLOTS_LINEAR  8-byte entries in ticket order: the consecutive tickets
+ *                    of one WaveFAA share lines, so the wavefront's slot
+ *                    atomics coalesce into a few line operations.            */
+typedef enum { GQ_SLOTS_REMAP = 0, GQ_SLOTS_PADDED = 1, GQ_SLOTS_LINEAR = 2 } gq_slot_mode;
 
 /* Option flags (gq_options.flags):
  *   GQ_OPT_FENCED      hand payloads over with an agent-scope release on the
@@ -72,13 +75,14 @@ typedef enum { GQ_SLOTS_REMAP = 0, GQ_SLOTS_PADDED = 1 } gq_slot_mode;
 #define GQ_OPT_WFQ_TUNING 2u
 
 typedef struct gq_options {
-    uint32_t slot_mode;        /* gq_slot_mode; default GQ_SLOTS_REMAP        */
+    uint32_t slot_mode;        /* gq_slot_mode (opts == NULL: GQ_SLOTS_LINEAR) */
     uint32_t flags;            /* GQ_OPT_* bits                               */
     uint64_t ymc_pool_cells;   /* G-WFQ-YMC pool size; 0 = 2^27 cells or
                                   16 * capacity, whichever is larger          */
     uint32_t wfq_patience_enq; /* fast-path attempts before the slow path     */
     uint32_t wfq_patience_deq;
-    uint32_t wfq_help_delay;   /* D: operations between peer-record checks    */
+    uint32_t wfq_help_delay;   /* D: operations between peer-record checks,
+                                  1..4095                                     */
     uint32_t reserved;
 } gq_options;
 
@@ -116,6 +120,7 @@ typedef struct gq_dev {
     uint32_t patience_deq;
     uint32_t help_delay;       /* G-WFQ help delay D                          */
     uint32_t pad1;
+    uint32_t *help_ctr;        /* G-WFQ per-lane <next peer:20 | ops:12>      */
 } gq_dev;
 
 typedef struct gq_stats {

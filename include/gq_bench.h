@@ -40,7 +40,7 @@ typedef struct gq_history {
 } gq_history;
 
 /* Mixed workload (Section V-A micro-benchmark shape, fixed op count): each of
- * `lanes` lanes (a multiple of 256, launched as lanes/256 workgroups of 256)
+ * `lanes` lanes (a multiple of 64; workgroups of 256 when lanes allows, else 64)
  * performs ops_per_lane operations; op r of lane g is an enqueue when the top
  * bit of r(seed, (g << 32) | r) is 0, else a dequeue.  Each op is tried once:
  * FULL/EMPTY outcomes are counted, not retried.  Lane g's j-th successful
@@ -48,6 +48,27 @@ typedef struct gq_history {
  * d_counts[4] += {ok_enq, ok_deq, full, empty}.  hist may be NULL.            */
 gq_status gq_run_mix(gq_queue *q, uint64_t seed, uint32_t lanes, uint32_t ops_per_lane,
                      uint64_t *d_counts, const gq_history *hist, void *stream);
+
+/* ---- many independent queues in one launch ---------------------------------
+ * A gq_multi binds nq queues of one kind; queue i gets lanes_per_queue[i]
+ * lanes (a multiple of 64, at most that queue's max_threads), i.e. whole
+ * wavefronts, laid out queue after queue; the total must fill whole
+ * workgroups of `block` (64, 128 or 256) lanes.  gq_multi_run_mix runs the
+ * mixed workload (as gq_run_mix, ops_per_lane each, lane ids counted within
+ * each queue, tokens and draws from the global lane id) on every queue in ONE
+ * kernel launch; d_counts[4 * i + 0..3] += {ok_enq, ok_deq, full, empty} of
+ * queue i.  gq_multi_capture records (seed bump + that launch) into a
+ * hipGraph on `stream` (which must not be the legacy default stream);
+ * gq_multi_replay launches it (each replay advances the seed by one).       */
+typedef struct gq_multi gq_multi;
+gq_status gq_multi_create(uint32_t nq, gq_queue *const *queues, const uint32_t *lanes_per_queue,
+                          uint32_t block, gq_multi **out);
+gq_status gq_multi_run_mix(gq_multi *m, uint64_t seed, uint32_t ops_per_lane, uint64_t *d_counts,
+                           const gq_history *hist, void *stream);
+gq_status gq_multi_capture(gq_multi *m, uint64_t seed, uint32_t ops_per_lane, uint64_t *d_counts,
+                           void *stream);
+gq_status gq_multi_replay(gq_multi *m, void *stream);
+gq_status gq_multi_destroy(gq_multi *m);
 
 /* Balanced workload (Section V-A "balanced kernel", fixed op count): every
  * lane performs `rounds` times (enqueue its next token; dequeue), each tried

@@ -21,7 +21,7 @@ GQ_ERR_INVALID, GQ_ERR_NOMEM, GQ_ERR_HIP, GQ_ERR_RESIDENCY = -1, -2, -3, -4
 GQ_ERR_CYCLE_BOUND, GQ_ERR_POOL_EXHAUSTED, GQ_ERR_DEVICE = -5, -6, -7
 
 KINDS = {"lfq": 0, "wfq": 1, "ymc": 2}
-SLOT_MODES = {"remap": 0, "padded": 1}
+SLOT_MODES = {"remap": 0, "padded": 1, "linear": 2}
 
 # Every symbol include/gq.h and include/gq_bench.h declare.
 EXPORTS = (
@@ -29,7 +29,8 @@ EXPORTS = (
     "gq_dequeue_batch", "gq_device_view", "gq_read_stats", "gq_clear_stats",
     "gq_check_error", "gq_status_str", "gq_run_mix", "gq_run_balanced", "gq_run_prodcons",
     "gq_run_script", "gq_probe_faa", "gq_probe_cas", "gq_probe_copy", "gq_probe_fence",
-    "gq_resident_blocks", "gq_device_info",
+    "gq_resident_blocks", "gq_device_info", "gq_multi_create", "gq_multi_run_mix",
+    "gq_multi_capture", "gq_multi_replay", "gq_multi_destroy",
 )
 
 
@@ -50,7 +51,7 @@ class _Options(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
-def make_options(slot_mode="remap", fenced=False, ymc_pool_cells=0, patience=None,
+def make_options(slot_mode="linear", fenced=False, ymc_pool_cells=0, patience=None,
                  help_delay=None) -> _Options:
     flags = GQ_OPT_FENCED if fenced else 0
     pe, pd, hd = 16, 64, 64
@@ -91,7 +92,7 @@ class _DevView(ctypes.Structure):
                 ("ymc_pool_cells", ctypes.c_uint64), ("ymc_ctr", ctypes.c_void_p),
                 ("ymc_handles", ctypes.c_void_p), ("patience_enq", ctypes.c_uint32),
                 ("patience_deq", ctypes.c_uint32), ("help_delay", ctypes.c_uint32),
-                ("pad1", ctypes.c_uint32)]
+                ("pad1", ctypes.c_uint32), ("help_ctr", ctypes.c_void_p)]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -125,6 +126,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gq_probe_fence": [P, U32, U32, U32, P],
         "gq_resident_blocks": [ctypes.c_char_p, I32, U32, P],
         "gq_device_info": [P, P, P, U32],
+        "gq_multi_create": [U32, P, P, U32, P],
+        "gq_multi_run_mix": [P, U64, U32, P, P, P],
+        "gq_multi_capture": [P, U64, U32, P, P],
+        "gq_multi_replay": [P, P],
+        "gq_multi_destroy": [P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -172,7 +178,7 @@ def _ptr(t) -> ctypes.c_void_p:
 
 
 def required_bytes(kind: str, capacity: int, item_width: int = 8, max_threads: int = 1,
-                   slot_mode: str = "remap", ymc_pool_cells: int = 0, **opts) -> int:
+                   slot_mode: str = "linear", ymc_pool_cells: int = 0, **opts) -> int:
     o = make_options(slot_mode, ymc_pool_cells=ymc_pool_cells, **opts)
     out = ctypes.c_uint64(0)
     _check(lib().gq_required_bytes(KINDS[kind], capacity, item_width, max_threads,
@@ -233,7 +239,7 @@ class Queue:
     """One device queue.  kind: 'lfq' | 'wfq' | 'ymc'."""
 
     def __init__(self, kind: str, capacity: int, item_width: int = 8, max_threads: int = 1,
-                 slot_mode: str = "remap", ymc_pool_cells: int = 0, fenced: bool = False,
+                 slot_mode: str = "linear", ymc_pool_cells: int = 0, fenced: bool = False,
                  patience=None, help_delay=None):
         torch = _torch()
         self.kind, self.capacity, self.item_width = kind, capacity, item_width
@@ -361,3 +367,41 @@ def device_info():
     name = ctypes.create_string_buffer(64)
     _check(lib().gq_device_info(ctypes.byref(cus), ctypes.byref(wave), name, 64), "gq_device_info")
     return {"cus": int(cus.value), "wave": int(wave.value), "arch": name.value.decode()}
+
+
+class Multi:
+    """Many independent queues driven by one kernel launch (and a hipGraph)."""
+
+    def __init__(self, queues, lanes_per_queue, block: int = 256):
+        self.queues = list(queues)
+        self.lanes = [int(x) for x in lanes_per_queue]
+        arr = (ctypes.c_void_p * len(self.queues))(*[q.handle for q in self.queues])
+        lp = (ctypes.c_uint32 * len(self.lanes))(*self.lanes)
+        h = ctypes.c_void_p(0)
+        _check(lib().gq_multi_create(len(self.queues), arr, lp, block, ctypes.byref(h)),
+               "gq_multi_create")
+        self._h = h
+
+    def run_mix(self, seed: int, ops_per_lane: int, counts, hist: History = None, stream=None):
+        hc = hist.c() if hist is not None else None
+        _check(lib().gq_multi_run_mix(self._h, seed, ops_per_lane, _ptr(counts),
+                                      ctypes.byref(hc) if hc is not None else None,
+                                      _stream(stream)), "gq_multi_run_mix")
+
+    def capture(self, seed: int, ops_per_lane: int, counts, stream):
+        _check(lib().gq_multi_capture(self._h, seed, ops_per_lane, _ptr(counts), _stream(stream)),
+               "gq_multi_capture")
+
+    def replay(self, stream):
+        _check(lib().gq_multi_replay(self._h, _stream(stream)), "gq_multi_replay")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gq_multi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

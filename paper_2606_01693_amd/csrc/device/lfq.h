@@ -50,11 +50,12 @@ struct Ring {
   int64_t* thr;
   uint32_t log2_2n;   // log2(2n)
   uint32_t log2_L;    // entries per line (remap mode)
-  uint32_t padded;    // 1: one entry per 128-byte line
+  uint32_t mode;      // gq_slot_mode
   int64_t thr_reset;  // 3n - 1
 
   __device__ __forceinline__ uint64_t* at(uint64_t j) const {
-    if (padded) return slots + (j << 4);  // 128-byte stride
+    if (mode == GQ_SLOTS_LINEAR) return slots + j;
+    if (mode == GQ_SLOTS_PADDED) return slots + (j << 4);  // 128-byte stride
     // remap: consecutive tickets land on different 128-byte lines
     const uint32_t log2_M = log2_2n - log2_L;
     const uint64_t pos = ((j & ((1ull << log2_M) - 1)) << log2_L) | (j >> log2_M);
@@ -88,7 +89,7 @@ __device__ __forceinline__ Ring make_ring(const gq_ring_view& v, const gq_dev& q
   r.thr = v.threshold;
   r.log2_2n = q.log2_cap + 1;
   r.log2_L = r.log2_2n < 4 ? r.log2_2n : 4;
-  r.padded = q.slot_mode == GQ_SLOTS_PADDED;
+  r.mode = q.slot_mode;
   r.thr_reset = threshold_reset(q);
   return r;
 }

@@ -100,8 +100,7 @@ struct Rec {
   uint64_t index;     // payload index of an enqueue request
   uint64_t req;       // <seq:62 | enqueue:1 | pending:1>, published last
   uint64_t next_seq;  // owner-private: sequence number of the next request
-  uint64_t help;      // owner-private (aq records): <next peer:32 | ops since check:32>
-  uint64_t pad[2];
+  uint64_t pad[3];
 };
 
 struct WRing {
@@ -433,11 +432,13 @@ __device__ __forceinline__ void help_peer(const WRing& r, uint32_t p) {
 }
 
 // Every D operations of a lane, inspect one peer's records on both rings.
+// The lane's counter and next peer live in one 32-bit word of a compact
+// per-lane array (a wavefront's 64 words share 2 lines).
 __device__ __forceinline__ void help_check(const gq_dev& q, uint32_t tid) {
-  Rec* me = &((Rec*)q.aq.records)[tid];
-  uint64_t h = me->help;
-  uint32_t cnt = (uint32_t)h + 1;
-  uint32_t peer = (uint32_t)(h >> 32);
+  uint32_t* hp = q.help_ctr + tid;
+  const uint32_t h = *hp;  // owner-private
+  uint32_t cnt = (h & 0xFFFu) + 1;
+  uint32_t peer = h >> 12;
   if (cnt >= q.help_delay) {
     cnt = 0;
     if (peer >= q.max_threads) peer = 0;
@@ -447,7 +448,7 @@ __device__ __forceinline__ void help_check(const gq_dev& q, uint32_t tid) {
     }
     peer = peer + 1 >= q.max_threads ? 0 : peer + 1;
   }
-  me->help = ((uint64_t)peer << 32) | cnt;
+  *hp = (peer << 12) | cnt;
 }
 
 // Inner enqueue of idx: fast path up to patience_enq attempts, then the slow path.

@@ -66,7 +66,8 @@ inline uint32_t ilog2(uint64_t x) {
 }
 
 struct Layout {
-  uint64_t slots_aq, slots_fq, data, rec_aq, rec_fq, own_aq, own_fq, ymc_pool, ymc_handles, total;
+  uint64_t slots_aq, slots_fq, data, rec_aq, rec_fq, own_aq, own_fq, help, ymc_pool, ymc_handles,
+      total;
 };
 
 bool kind_supported(gq_kind kind) {
@@ -90,16 +91,16 @@ gq_status plan(gq_kind kind, uint64_t n, uint32_t w, uint32_t k, const gq_option
   if (!is_pow2(n) || n < 2 || n > (1ull << 30)) return GQ_ERR_INVALID;
   if (w != 4 && w != 8) return GQ_ERR_INVALID;
   if (k == 0 || k > (1u << 24)) return GQ_ERR_INVALID;
-  if (o && ((o->flags & ~(GQ_OPT_FENCED | GQ_OPT_WFQ_TUNING)) || o->slot_mode > GQ_SLOTS_PADDED))
+  if (o && ((o->flags & ~(GQ_OPT_FENCED | GQ_OPT_WFQ_TUNING)) || o->slot_mode > GQ_SLOTS_LINEAR))
     return GQ_ERR_INVALID;
   if (kind == GQ_WFQ) {
     if (k >= (1u << wfq::TID_BITS)) return GQ_ERR_INVALID;
     const bool tuned = o && (o->flags & GQ_OPT_WFQ_TUNING);
     const uint64_t D = tuned ? o->wfq_help_delay : 64;
-    if (tuned && D == 0) return GQ_ERR_INVALID;
+    if (tuned && (D == 0 || D > 4095)) return GQ_ERR_INVALID;
     if (!wfq_cycle_bound_ok(n, k, D)) return GQ_ERR_CYCLE_BOUND;
   }
-  const uint32_t mode = o ? o->slot_mode : GQ_SLOTS_REMAP;
+  const uint32_t mode = o ? o->slot_mode : GQ_SLOTS_LINEAR;
   const uint64_t slot_bytes = 2 * n * (mode == GQ_SLOTS_PADDED ? 128 : 8);
   uint64_t off = kCtrlBytes;
   L->slots_aq = off;
@@ -108,7 +109,7 @@ gq_status plan(gq_kind kind, uint64_t n, uint32_t w, uint32_t k, const gq_option
   off = align_up(off + slot_bytes, 4096);
   L->data = off;
   off = align_up(off + n * w, 4096);
-  L->rec_aq = L->rec_fq = L->own_aq = L->own_fq = L->ymc_pool = L->ymc_handles = 0;
+  L->rec_aq = L->rec_fq = L->own_aq = L->own_fq = L->help = L->ymc_pool = L->ymc_handles = 0;
   if (kind == GQ_WFQ) {
     L->rec_aq = off;
     off = align_up(off + (uint64_t)k * sizeof(wfq::Rec), 4096);
@@ -118,6 +119,8 @@ gq_status plan(gq_kind kind, uint64_t n, uint32_t w, uint32_t k, const gq_option
     off = align_up(off + 2 * n * 8, 4096);
     L->own_fq = off;
     off = align_up(off + 2 * n * 8, 4096);
+    L->help = off;
+    off = align_up(off + (uint64_t)k * 4, 4096);
   }
   if (kind == GQ_WFQ_YMC) {
     const uint64_t cells = (o && o->ymc_pool_cells) ? o->ymc_pool_cells : ymc_default_cells(n);
@@ -183,9 +186,9 @@ __global__ void k_init_wfq(gq_dev q) {
       st(&R->index, 0ull);
       st(&R->req, 0ull);
       st(&R->next_seq, 1ull);
-      const uint64_t peer = (t + 1) % q.max_threads;
-      st(&R->help, (peer << 32) | (t % (q.help_delay ? q.help_delay : 1)));
     }
+    const uint32_t peer = (uint32_t)((t + 1) % q.max_threads);
+    st(q.help_ctr + t, (peer << 12) | (uint32_t)(t % (q.help_delay ? q.help_delay : 1)));
   }
   if (g0 == 0) {
     st(q.aq.head, 0ull);
@@ -301,10 +304,12 @@ __device__ __forceinline__ uint64_t end_stamp() {
 }
 
 // ---- mixed workload --------------------------------------------------------
+// One lane's part of the mixed workload on queue q: `ops` operations, op r an
+// enqueue iff the top bit of r(seed, (g << 32) | r) is 0, tried once.  g is
+// the lane's global id (tokens and draws), tid its id within the queue.
 template <int KIND, bool REC>
-__global__ __launch_bounds__(256) void k_mix(gq_dev q, uint64_t seed, uint32_t ops,
-                                             uint64_t* counts, Rec rec) {
-  const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+__device__ __forceinline__ void mix_lane(const gq_dev& q, uint64_t g, uint32_t tid, uint64_t seed,
+                                         uint32_t ops, uint64_t* counts, const Rec& rec) {
   uint64_t seq = 0, ok_e = 0, ok_d = 0, full = 0, empty = 0;
   uint32_t cf = 0;
   for (uint32_t r = 0; r < ops; r++) {
@@ -314,11 +319,11 @@ __global__ __launch_bounds__(256) void k_mix(gq_dev q, uint64_t seed, uint32_t o
     int s;
     if (is_enq) {
       v = (g << 32) | (seq + 1);
-      s = gq_enqueue_k<KIND>(q, v, (uint32_t)g, cf);
+      s = gq_enqueue_k<KIND>(q, v, tid, cf);
       if (s == GQ_OK) { seq++; ok_e++; } else full++;
     } else {
       v = 0;
-      s = gq_dequeue_k<KIND>(q, &v, (uint32_t)g, cf);
+      s = gq_dequeue_k<KIND>(q, &v, tid, cf);
       if (s == GQ_OK) ok_d++; else { empty++; v = 0; }
     }
     if (REC) rec.put(g, r, is_enq ? 0 : 1, s, v, t0, end_stamp());
@@ -329,6 +334,31 @@ __global__ __launch_bounds__(256) void k_mix(gq_dev q, uint64_t seed, uint32_t o
   wave_add(counts + 2, full);
   wave_add(counts + 3, empty);
   wave_add(q.stats + S_CAS_FAIL, cf);
+}
+
+template <int KIND, bool REC>
+__global__ __launch_bounds__(256) void k_mix(gq_dev q, uint64_t seed, uint32_t ops,
+                                             uint64_t* counts, Rec rec) {
+  const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  mix_lane<KIND, REC>(q, g, (uint32_t)g, seed, ops, counts, rec);
+}
+
+// Many independent queues in one launch: wavefront w works on queue
+// wave_q[w]; lane ids inside a queue start at q_lane0[queue].  The seed is
+// read from device memory so that a captured graph can advance it.
+template <int KIND, bool REC>
+__global__ __launch_bounds__(256) void k_multi_mix(const gq_dev* qs, const uint32_t* wave_q,
+                                                   const uint32_t* q_lane0, const uint64_t* seed,
+                                                   uint32_t ops, uint64_t* counts, Rec rec) {
+  const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint32_t qi = __builtin_amdgcn_readfirstlane(wave_q[g / 64]);
+  const gq_dev q = qs[qi];
+  const uint32_t tid = (uint32_t)(g - q_lane0[qi]);
+  mix_lane<KIND, REC>(q, g, tid, ld(seed), ops, counts + 4 * (uint64_t)qi, rec);
+}
+
+__global__ void k_seed(uint64_t* seed, uint64_t value, uint32_t bump) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) st(seed, bump ? ld(seed) + 1 : value);
 }
 
 // ---- balanced workload -----------------------------------------------------
@@ -591,6 +621,7 @@ gq_status gq_create(gq_kind kind, uint64_t capacity, uint32_t item_width, uint32
   q->w = item_width;
   q->k = max_threads;
   memset(&q->opt, 0, sizeof(q->opt));
+  q->opt.slot_mode = GQ_SLOTS_LINEAR;
   if (opts) q->opt = *opts;
   q->L = L;
   if (dev_buf) {
@@ -653,6 +684,7 @@ gq_status gq_create(gq_kind kind, uint64_t capacity, uint32_t item_width, uint32
     d.fq.records = q->buf + L.rec_fq;
     d.aq.owner = (uint64_t*)(q->buf + L.own_aq);
     d.fq.owner = (uint64_t*)(q->buf + L.own_fq);
+    d.help_ctr = (uint32_t*)(q->buf + L.help);
   }
   d.err = (uint64_t*)(q->buf + OFF_ERR);
   d.stats = (uint64_t*)(q->buf + OFF_STATS);
@@ -773,7 +805,8 @@ static Rec make_rec(const gq_history* h) {
 template <int KIND>
 static void launch_mix(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t ops, uint64_t* counts,
                        const gq_history* hist, hipStream_t s) {
-  const dim3 grid(lanes / kBlock), block(kBlock);
+  const uint32_t b = lanes % kBlock == 0 ? kBlock : 64;
+  const dim3 grid(lanes / b), block(b);
   const Rec rec = make_rec(hist);
   if (hist) LAUNCH((k_mix<KIND, true>), grid, block, 0, s, q->dev, seed, ops, counts, rec);
   else LAUNCH((k_mix<KIND, false>), grid, block, 0, s, q->dev, seed, ops, counts, rec);
@@ -781,7 +814,7 @@ static void launch_mix(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t ops,
 
 gq_status gq_run_mix(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t ops_per_lane,
                      uint64_t* d_counts, const gq_history* hist, void* stream) {
-  if (!q || !d_counts || lanes == 0 || lanes % kBlock || lanes > q->k) return GQ_ERR_INVALID;
+  if (!q || !d_counts || lanes == 0 || lanes % 64 || lanes > q->k) return GQ_ERR_INVALID;
   if (hist && (!hist->val || !hist->call || !hist->ret || !hist->opst)) return GQ_ERR_INVALID;
   KIND_SWITCH(q->kind, launch_mix<K>(q, seed, lanes, ops_per_lane, d_counts, hist, S(stream)));
   HIP_OK(hipGetLastError());
@@ -961,3 +994,152 @@ gq_status gq_device_info(uint32_t* cus, uint32_t* wave, char* name, uint32_t len
 }
 
 
+
+// ---- many queues in one launch ----------------------------------------------
+struct gq_multi {
+  gq_kind kind;
+  uint32_t nq, waves, block;
+  gq_dev* d_qs;
+  uint32_t* d_wave_q;
+  uint32_t* d_q_lane0;
+  uint64_t* d_seed;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  bool captured;
+};
+
+gq_status gq_multi_create(uint32_t nq, gq_queue* const* queues, const uint32_t* lanes_per_queue,
+                          uint32_t block, gq_multi** out) {
+  if (!out || !queues || !lanes_per_queue || nq == 0 || (block != 64 && block != 128 &&
+      block != 256))
+    return GQ_ERR_INVALID;
+  *out = nullptr;
+  uint64_t waves = 0;
+  for (uint32_t i = 0; i < nq; i++) {
+    if (!queues[i] || queues[i]->kind != queues[0]->kind) return GQ_ERR_INVALID;
+    const uint32_t L = lanes_per_queue[i];
+    if (L == 0 || L % 64 || L > queues[i]->k) return GQ_ERR_INVALID;
+    waves += L / 64;
+  }
+  const uint32_t wpb = block / 64;
+  const uint64_t waves_padded = (waves + wpb - 1) / wpb * wpb;
+  if (waves_padded * 64 > (1ull << 31)) return GQ_ERR_INVALID;
+  // The wavefronts must fill whole workgroups: a ragged total is refused.
+  if (waves_padded != waves) return GQ_ERR_INVALID;
+  gq_dev* h_qs = (gq_dev*)malloc(sizeof(gq_dev) * nq);
+  uint32_t* h_wave_q = (uint32_t*)malloc(sizeof(uint32_t) * waves);
+  uint32_t* h_lane0 = (uint32_t*)malloc(sizeof(uint32_t) * nq);
+  if (!h_qs || !h_wave_q || !h_lane0) {
+    free(h_qs); free(h_wave_q); free(h_lane0);
+    return GQ_ERR_NOMEM;
+  }
+  uint64_t w = 0;
+  for (uint32_t i = 0; i < nq; i++) {
+    h_qs[i] = queues[i]->dev;
+    h_lane0[i] = (uint32_t)(w * 64);
+    for (uint32_t j = 0; j < lanes_per_queue[i] / 64; j++) h_wave_q[w++] = i;
+  }
+  gq_multi* m = new (std::nothrow) gq_multi();
+  if (!m) { free(h_qs); free(h_wave_q); free(h_lane0); return GQ_ERR_NOMEM; }
+  m->kind = queues[0]->kind;
+  m->nq = nq;
+  m->waves = (uint32_t)waves;
+  m->block = block;
+  m->captured = false;
+  gq_status st = GQ_OK;
+  if (hipMalloc(&m->d_qs, sizeof(gq_dev) * nq) != hipSuccess ||
+      hipMalloc(&m->d_wave_q, sizeof(uint32_t) * waves) != hipSuccess ||
+      hipMalloc(&m->d_q_lane0, sizeof(uint32_t) * nq) != hipSuccess ||
+      hipMalloc(&m->d_seed, 256) != hipSuccess)
+    st = GQ_ERR_NOMEM;
+  if (st == GQ_OK &&
+      (hipMemcpy(m->d_qs, h_qs, sizeof(gq_dev) * nq, hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(m->d_wave_q, h_wave_q, sizeof(uint32_t) * waves, hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(m->d_q_lane0, h_lane0, sizeof(uint32_t) * nq, hipMemcpyHostToDevice) != hipSuccess))
+    st = GQ_ERR_HIP;
+  free(h_qs); free(h_wave_q); free(h_lane0);
+  if (st != GQ_OK) {
+    gq_multi_destroy(m);
+    return st;
+  }
+  *out = m;
+  return GQ_OK;
+}
+
+template <int KIND>
+static void launch_multi(gq_multi* m, uint32_t ops, uint64_t* counts, const gq_history* hist,
+                         hipStream_t s) {
+  const dim3 grid(m->waves * 64 / m->block), block(m->block);
+  const Rec rec = make_rec(hist);
+  if (hist)
+    LAUNCH((k_multi_mix<KIND, true>), grid, block, 0, s, m->d_qs, m->d_wave_q, m->d_q_lane0,
+           m->d_seed, ops, counts, rec);
+  else
+    LAUNCH((k_multi_mix<KIND, false>), grid, block, 0, s, m->d_qs, m->d_wave_q, m->d_q_lane0,
+           m->d_seed, ops, counts, rec);
+}
+
+gq_status gq_multi_run_mix(gq_multi* m, uint64_t seed, uint32_t ops_per_lane, uint64_t* d_counts,
+                           const gq_history* hist, void* stream) {
+  if (!m || !d_counts) return GQ_ERR_INVALID;
+  if (hist && (!hist->val || !hist->call || !hist->ret || !hist->opst)) return GQ_ERR_INVALID;
+  LAUNCH(k_seed, dim3(1), dim3(64), 0, S(stream), m->d_seed, seed, 0u);
+  HIP_OK(hipGetLastError());
+  KIND_SWITCH(m->kind, launch_multi<K>(m, ops_per_lane, d_counts, hist, S(stream)));
+  HIP_OK(hipGetLastError());
+  return GQ_OK;
+}
+
+gq_status gq_multi_capture(gq_multi* m, uint64_t seed, uint32_t ops_per_lane, uint64_t* d_counts,
+                           void* stream) {
+  if (!m || !d_counts || !stream) return GQ_ERR_INVALID;
+  if (m->captured) {
+    (void)hipGraphExecDestroy(m->exec);
+    (void)hipGraphDestroy(m->graph);
+    m->captured = false;
+  }
+  // the first replay runs with seed + 1, each later one with the next seed
+  LAUNCH(k_seed, dim3(1), dim3(64), 0, S(stream), m->d_seed, seed, 0u);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamBeginCapture(S(stream), hipStreamCaptureModeRelaxed));
+  LAUNCH(k_seed, dim3(1), dim3(64), 0, S(stream), m->d_seed, 0ull, 1u);
+  gq_status st = GQ_OK;
+  switch (m->kind) {
+    case GQ_LFQ: launch_multi<GQ_LFQ>(m, ops_per_lane, d_counts, nullptr, S(stream)); break;
+    case GQ_WFQ: launch_multi<GQ_WFQ>(m, ops_per_lane, d_counts, nullptr, S(stream)); break;
+    case GQ_WFQ_YMC: launch_multi<GQ_WFQ_YMC>(m, ops_per_lane, d_counts, nullptr, S(stream)); break;
+    default: st = GQ_ERR_INVALID;
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(S(stream), &g);
+  if (st != GQ_OK) return st;
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture", __LINE__);
+  e = hipGraphInstantiate(&m->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(e, "hipGraphInstantiate", __LINE__);
+  }
+  m->graph = g;
+  m->captured = true;
+  return GQ_OK;
+}
+
+gq_status gq_multi_replay(gq_multi* m, void* stream) {
+  if (!m || !m->captured) return GQ_ERR_INVALID;
+  HIP_OK(hipGraphLaunch(m->exec, S(stream)));
+  return GQ_OK;
+}
+
+gq_status gq_multi_destroy(gq_multi* m) {
+  if (!m) return GQ_ERR_INVALID;
+  if (m->captured) {
+    (void)hipGraphExecDestroy(m->exec);
+    (void)hipGraphDestroy(m->graph);
+  }
+  if (m->d_qs) (void)hipFree(m->d_qs);
+  if (m->d_wave_q) (void)hipFree(m->d_wave_q);
+  if (m->d_q_lane0) (void)hipFree(m->d_q_lane0);
+  if (m->d_seed) (void)hipFree(m->d_seed);
+  delete m;
+  return GQ_OK;
+}

@@ -19,7 +19,7 @@ KINDS = ["lfq", "wfq", "ymc"]
 BOUNDED = {"lfq": True, "wfq": True, "ymc": False}
 
 
-def make_queue(kind, n, width=8, lanes=1024, slot_mode="remap", **opts):
+def make_queue(kind, n, width=8, lanes=1024, slot_mode="linear", **opts):
     import paper_2606_01693_amd as gq
     print(f"[case] kind={kind} n={n} width={width} lanes={lanes} slots={slot_mode} {opts}",
           flush=True)
@@ -272,7 +272,7 @@ def test_tiny_histories_linearizable(kind, chunk):
 # ---------------------------------------------------------------------------
 # Mixed 50/50 workload with recorded histories
 # ---------------------------------------------------------------------------
-def run_mix_checked(kind, n, lanes, ops, seed, slot_mode="remap", do_prefill=True, **opts):
+def run_mix_checked(kind, n, lanes, ops, seed, slot_mode="linear", do_prefill=True, **opts):
     import paper_2606_01693_amd as gq
     T = torch()
     q = make_queue(kind, n, lanes=lanes, slot_mode=slot_mode, **opts)
@@ -292,8 +292,9 @@ def run_mix_checked(kind, n, lanes, ops, seed, slot_mode="remap", do_prefill=Tru
     assert np.array_equal(hist.op, roles)
     c = counts.cpu().tolist()
     assert c[0] == int(((hist.op == 0) & (hist.st == 0)).sum())
-    drain = drain_fifo(q, n if BOUNDED[kind] else len(pre) + c[0])
-    assert len(drain) == len(pre) + c[0] - c[1]
+    expect = len(pre) + c[0] - c[1]
+    drain = drain_fifo(q, n if BOUNDED[kind] else expect + 1)
+    assert len(drain) == expect
     rep = check_history(hist, drain, prefill=pre, capacity=cap_of(kind, n))
     assert_clean(rep, hist, drain, pre, tag=f"mix_{kind}_{n}_{lanes}_{ops}_{slot_mode}")
     return c
@@ -306,9 +307,12 @@ def test_mix_history(kind, n, lanes, ops):
     run_mix_checked(kind, n, lanes, ops, workloads.run_seed(2, n))
 
 
-@pytest.mark.parametrize("kind", KINDS)
-def test_mix_history_padded_slots(kind):
-    run_mix_checked(kind, 1 << 10, 16384, 32, workloads.run_seed(2, 77), slot_mode="padded")
+@pytest.mark.parametrize("kind", ["lfq", "wfq"])
+@pytest.mark.parametrize("slot_mode", ["padded", "linear"])
+@pytest.mark.parametrize("n", [4, 1 << 10])
+def test_mix_history_slot_layouts(kind, slot_mode, n):
+    lanes = 1024 if n < 64 else 16384
+    run_mix_checked(kind, n, lanes, 32, workloads.run_seed(2, 77), slot_mode=slot_mode)
 
 
 @pytest.mark.parametrize("kind", KINDS)
