@@ -70,6 +70,19 @@ gq_status gq_multi_capture(gq_multi *m, uint64_t seed, uint32_t ops_per_lane, ui
 gq_status gq_multi_replay(gq_multi *m, void *stream);
 gq_status gq_multi_destroy(gq_multi *m);
 
+/* Queue-driven level-synchronous BFS (Section V-B) in one persistent launch of
+ * `lanes` lanes in workgroups of `block` (64..256): two empty queues qa, qb
+ * of the same kind with item_width 4 (bounded kinds: capacity >= nv; a
+ * G-WFQ-YMC pool must hold nv + levels * lanes cells), CSR graph (uint32
+ * offsets[nv + 1], cols[offsets[nv]]), root < nv.  d_level[nv] receives hop
+ * distances (0xFFFFFFFF = unreached).  d_ctl: caller-owned scratch of at least
+ * 1 KiB; after the run d_ctl[160] = number of levels, d_ctl[192] = adjacency
+ * entries scanned.  All workgroups must be co-resident (GQ_ERR_RESIDENCY
+ * otherwise).  Device-side failures latch in qa's error word.               */
+gq_status gq_bfs(gq_queue *qa, gq_queue *qb, const uint32_t *d_offsets, const uint32_t *d_cols,
+                 uint32_t nv, uint32_t root, uint32_t *d_level, uint32_t lanes, uint32_t block,
+                 uint64_t *d_ctl, void *stream);
+
 /* Balanced workload (Section V-A "balanced kernel", fixed op count): every
  * lane performs `rounds` times (enqueue its next token; dequeue), each tried
  * once.  Tokens as in gq_run_mix.  d_counts[4] as above.                      */

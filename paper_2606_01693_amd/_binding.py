@@ -30,7 +30,7 @@ EXPORTS = (
     "gq_check_error", "gq_status_str", "gq_run_mix", "gq_run_balanced", "gq_run_prodcons",
     "gq_run_script", "gq_probe_faa", "gq_probe_cas", "gq_probe_copy", "gq_probe_fence",
     "gq_resident_blocks", "gq_device_info", "gq_multi_create", "gq_multi_run_mix",
-    "gq_multi_capture", "gq_multi_replay", "gq_multi_destroy",
+    "gq_multi_capture", "gq_multi_replay", "gq_multi_destroy", "gq_bfs",
 )
 
 
@@ -131,6 +131,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gq_multi_capture": [P, U64, U32, P, P],
         "gq_multi_replay": [P, P],
         "gq_multi_destroy": [P],
+        "gq_bfs": [P, P, P, P, U32, U32, P, U32, U32, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -405,3 +406,10 @@ class Multi:
             self.close()
         except Exception:
             pass
+
+
+def bfs(qa: Queue, qb: Queue, offsets, cols, root: int, level, lanes: int, block: int, ctl,
+        stream=None):
+    """Launch the queue-driven BFS; offsets/cols/level/ctl are CUDA tensors."""
+    _check(lib().gq_bfs(qa.handle, qb.handle, _ptr(offsets), _ptr(cols), offsets.numel() - 1,
+                        root, _ptr(level), lanes, block, _ptr(ctl), _stream(stream)), "gq_bfs")

@@ -46,6 +46,10 @@ __device__ __forceinline__ bool cas(uint64_t* p, uint64_t& expected, uint64_t de
   return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
                                               __ATOMIC_RELAXED, GQ_AGENT);
 }
+__device__ __forceinline__ bool cas32(uint32_t* p, uint32_t& expected, uint32_t desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
+                                              __ATOMIC_RELAXED, GQ_AGENT);
+}
 __device__ __forceinline__ bool cas_rel(uint64_t* p, uint64_t& expected, uint64_t desired) {
   return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELEASE,
                                               __ATOMIC_RELAXED, GQ_AGENT);

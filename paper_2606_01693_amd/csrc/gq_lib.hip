@@ -515,6 +515,8 @@ __global__ void k_probe_fence(uint64_t* lines, uint32_t iters, uint32_t mode) {
 
 __global__ void k_sink() {}
 
+#include "gq_bfs.inc"
+
 }  // namespace
 
 // ============================================================================
@@ -1141,5 +1143,41 @@ gq_status gq_multi_destroy(gq_multi* m) {
   if (m->d_q_lane0) (void)hipFree(m->d_q_lane0);
   if (m->d_seed) (void)hipFree(m->d_seed);
   delete m;
+  return GQ_OK;
+}
+
+// ---- queue-driven BFS ----------------------------------------------------------
+template <int KIND>
+static const void* bfs_fn() { return (const void*)bfs::k_bfs<KIND>; }
+
+template <int KIND>
+static void launch_bfs(gq_queue* qa, gq_queue* qb, const uint32_t* off, const uint32_t* cols,
+                       uint32_t nv, uint32_t root, uint32_t* level, uint64_t* ctl, uint32_t lanes,
+                       uint32_t block, hipStream_t s) {
+  const uint32_t nblocks = lanes / block;
+  LAUNCH((bfs::k_bfs<KIND>), dim3(nblocks), dim3(block), 0, s, qa->dev, qb->dev, off, cols, nv,
+         root, level, ctl, nblocks);
+}
+
+gq_status gq_bfs(gq_queue* qa, gq_queue* qb, const uint32_t* d_offsets, const uint32_t* d_cols,
+                 uint32_t nv, uint32_t root, uint32_t* d_level, uint32_t lanes, uint32_t block,
+                 uint64_t* d_ctl, void* stream) {
+  if (!qa || !qb || qa == qb || !d_offsets || !d_cols || !d_level || !d_ctl || nv == 0 ||
+      root >= nv || qa->kind != qb->kind || qa->w != 4 || qb->w != 4 || block == 0 ||
+      block > 256 || block % 64 || lanes == 0 || lanes % block || lanes > qa->k || lanes > qb->k)
+    return GQ_ERR_INVALID;
+  if (qa->kind != GQ_WFQ_YMC && (qa->n < nv || qb->n < nv)) return GQ_ERR_INVALID;
+  const void* fn = nullptr;
+  KIND_SWITCH(qa->kind, fn = bfs_fn<K>());
+  uint32_t resident = 0;
+  gq_status st = resident_blocks_of(fn, block, &resident);
+  if (st != GQ_OK) return st;
+  if (lanes / block > resident) return GQ_ERR_RESIDENCY;
+  LAUNCH(bfs::k_bfs_init, dim3(grid_for(nv, kBlock, 8192)), dim3(kBlock), 0, S(stream), d_level, nv,
+         d_ctl);
+  HIP_OK(hipGetLastError());
+  KIND_SWITCH(qa->kind, launch_bfs<K>(qa, qb, d_offsets, d_cols, nv, root, d_level, d_ctl, lanes,
+                                      block, S(stream)));
+  HIP_OK(hipGetLastError());
   return GQ_OK;
 }

@@ -22,7 +22,47 @@ small uint32 run uses (producer_id << 20) | seq instead (its payload is 32-bit).
 """
 from __future__ import annotations
 
+import ctypes
+import os
+import subprocess
+
 import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_GG_SRC = os.path.join(_HERE, "graphgen.c")
+_GG_LIB = os.path.join(_HERE, "libgraphgen.so")
+
+
+def build() -> str:
+    """Compile the C graph builders (gcc, always rebuilds)."""
+    subprocess.run(["gcc", "-O3", "-std=c11", "-shared", "-fPIC", "-pthread", _GG_SRC, "-o",
+                    _GG_LIB + ".tmp"], check=True)
+    os.replace(_GG_LIB + ".tmp", _GG_LIB)
+    return _GG_LIB
+
+
+_gg = None
+
+
+def _threads() -> int:
+    return max(1, min(os.cpu_count() or 1, 16))
+
+
+def _graphgen():
+    global _gg
+    if _gg is None:
+        if not os.path.exists(_GG_LIB):
+            build()
+        L = ctypes.CDLL(_GG_LIB)
+        P, U32, U64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+        L.wl_rmat_pairs.argtypes = [U32, U64, U64, U64, U64, U64, P, P, U32, P]
+        L.wl_rmat_pairs.restype = ctypes.c_int
+        L.wl_csr.argtypes = [U64, U64, P, P, P, P]
+        L.wl_csr.restype = ctypes.c_int64
+        L.wl_csr_par.argtypes = [U64, U64, P, P, P, P, U32]
+        L.wl_csr_par.restype = ctypes.c_int64
+        _gg = L
+    return _gg
 
 GAMMA = np.uint64(0x9E3779B97F4A7C15)
 MIX1 = np.uint64(0xBF58476D1CE4E5B9)
@@ -138,22 +178,43 @@ def _csr_from_pairs(nv: int, src: np.ndarray, dst: np.ndarray):
     return offsets.astype(np.uint32), cols
 
 
+def _csr_fast(nv: int, src: np.ndarray, dst: np.ndarray):
+    src = np.ascontiguousarray(src, dtype=np.uint64)
+    dst = np.ascontiguousarray(dst, dtype=np.uint64)
+    off = np.zeros(nv + 1, dtype=np.uint32)
+    cols = np.zeros(2 * len(src) + 1, dtype=np.uint32)
+    nnz = _graphgen().wl_csr_par(nv, len(src), src.ctypes.data, dst.ctypes.data,
+                                 off.ctypes.data, cols.ctypes.data, _threads())
+    if nnz < 0:
+        raise ValueError("graph too large for uint32 offsets")
+    return off, cols[:nnz].copy()
+
+
 def rmat_graph(scale: int, edgefactor: int = 16, a=0.57, b=0.19, c=0.19,
-               seed: int = BASE_SEED, permute: bool = True):
+               seed: int = BASE_SEED, permute: bool = True, fast: bool = True):
     """Graph500-style R-MAT graph (no noise), seeded vertex permutation.
 
     Edge e, level l: the quadrant is chosen by u = splitmix64(seed,
     (e << 8) | l) / 2^64 against the cumulative probabilities a, a+b, a+b+c.
-    Then symmetrised, self loops dropped, duplicates removed.
+    Then symmetrised, self loops dropped, duplicates removed.  fast=True uses
+    the C builders (identical output), fast=False the numpy definition below.
     """
     nv = 1 << scale
     ne = edgefactor * nv
-    e = np.arange(ne, dtype=np.uint64)
-    src = np.zeros(ne, dtype=np.uint64)
-    dst = np.zeros(ne, dtype=np.uint64)
     ta = np.uint64(int(a * 2**64) - 1)
     tab = np.uint64(int((a + b) * 2**64) - 1)
     tabc = np.uint64(int((a + b + c) * 2**64) - 1)
+    if fast:
+        src = np.zeros(ne, dtype=np.uint64)
+        dst = np.zeros(ne, dtype=np.uint64)
+        perm = np.ascontiguousarray(_rmat_perm(nv, seed)) if permute else None
+        _graphgen().wl_rmat_pairs(scale, ne, int(seed) & (2**64 - 1), int(ta), int(tab), int(tabc),
+                                  src.ctypes.data, dst.ctypes.data, _threads(),
+                                  perm.ctypes.data if perm is not None else None)
+        return _csr_fast(nv, src, dst)
+    e = np.arange(ne, dtype=np.uint64)
+    src = np.zeros(ne, dtype=np.uint64)
+    dst = np.zeros(ne, dtype=np.uint64)
     for lvl in range(scale):
         u = splitmix64(seed, (e << np.uint64(8)) | np.uint64(lvl))
         right = ((u >= ta) & (u < tab)) | (u >= tabc)   # quadrants b, d
@@ -162,14 +223,19 @@ def rmat_graph(scale: int, edgefactor: int = 16, a=0.57, b=0.19, c=0.19,
         src |= np.where(down, bit, np.uint64(0))
         dst |= np.where(right, bit, np.uint64(0))
     if permute:
-        perm = np.argsort(splitmix64(seed ^ 0x5DEECE66D, np.arange(nv, dtype=np.uint64)),
-                          kind="stable").astype(np.uint64)
+        perm = _rmat_perm(nv, seed)
         src = perm[src.astype(np.int64)]
         dst = perm[dst.astype(np.int64)]
     return _csr_from_pairs(nv, src, dst)
 
 
-def grid_graph(rows: int, cols: int):
+def _rmat_perm(nv: int, seed: int) -> np.ndarray:
+    """Seeded vertex relabelling: vertex v becomes the rank of its draw."""
+    return np.argsort(splitmix64(seed ^ 0x5DEECE66D, np.arange(nv, dtype=np.uint64)),
+                      kind="stable").astype(np.uint64)
+
+
+def grid_graph(rows: int, cols: int, fast: bool = True):
     """rows x cols 4-neighbour grid, vertex id r * cols + c."""
     nv = rows * cols
     v = np.arange(nv, dtype=np.uint64).reshape(rows, cols)
@@ -177,7 +243,7 @@ def grid_graph(rows: int, cols: int):
     down = (v[:-1, :].ravel(), v[1:, :].ravel())
     src = np.concatenate([right[0], down[0]])
     dst = np.concatenate([right[1], down[1]])
-    return _csr_from_pairs(nv, src, dst)
+    return _csr_fast(nv, src, dst) if fast else _csr_from_pairs(nv, src, dst)
 
 
 def bfs_root(offsets: np.ndarray, seed: int) -> int:
