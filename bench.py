@@ -130,6 +130,176 @@ def cpu_baselines(seed, sample_lanes):
     return replay, locked
 
 
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+BFS_LANES = {"rmat22_ef16": (2048, 8192, 32768), "grid4096": (512, 2048, 8192)}
+
+
+def bench_bfs(gq, torch, kinds=("lfq",), runs=3):
+    """Queue-driven BFS GTEPS on the R-MAT scale-22 and 4096^2 grid inputs.
+    GTEPS = (sum of degrees of reached vertices / 2) / time (undirected edges
+    of the traversed component per second).  Levels are compared with the
+    CPU BFS (oracle O7), which is also timed as the 1-core baseline."""
+    import oracle
+    import workloads
+    out = {}
+    seed = workloads.run_seed(4, 0)
+    t0 = time.perf_counter()
+    graphs = {"rmat22_ef16": workloads.rmat_graph(22, 16, seed=seed),
+              "grid4096": workloads.grid_graph(4096, 4096)}
+    log(f"[bench] graphs built in {time.perf_counter() - t0:.1f} s")
+    roots = {"rmat22_ef16": workloads.bfs_root(graphs["rmat22_ef16"][0], seed),
+             "grid4096": int(np.random.default_rng(workloads.run_seed(4, 1)).integers(0, 4096 ** 2))}
+    for name, (off, cols) in graphs.items():
+        nv = len(off) - 1
+        root = roots[name]
+        c0 = time.perf_counter()
+        exp, nl, scanned = oracle.bfs(off, cols, root)
+        cpu_s = time.perf_counter() - c0
+        log(f"[bench] cpu bfs {name}: {cpu_s * 1e3:.1f} ms, {nl} levels")
+        edges = scanned / 2
+        d_off = torch.tensor(off.astype(np.int32), device="cuda")
+        d_cols = torch.tensor(cols.astype(np.int32), device="cuda")
+        level = torch.empty(nv, dtype=torch.int32, device="cuda")
+        ctl = torch.zeros(512, dtype=torch.int64, device="cuda")
+        cap = 1 << int(np.ceil(np.log2(nv)))
+        res = {"vertices": nv, "csr_entries": int(len(cols)), "root": root, "levels": nl,
+               "edges_traversed": int(edges), "cpu_bfs_gteps": edges / cpu_s / 1e9,
+               "cpu_bfs_ms": cpu_s * 1e3, "runs": {}}
+        best = None
+        for kind in kinds:
+            for lanes in BFS_LANES[name]:
+                try:
+                    qa = gq.Queue(kind, cap, item_width=4, max_threads=lanes)
+                    qb = gq.Queue(kind, cap, item_width=4, max_threads=lanes)
+                except gq.GQError as e:
+                    log(f"[bench] bfs {name} {kind} lanes={lanes}: {e}")
+                    continue
+                ms = []
+                ok = True
+                for r in range(runs + 1):
+                    qa.reset()
+                    qb.reset()
+                    e0, e1 = _events(torch)
+                    e0.record()
+                    try:
+                        gq.bfs(qa, qb, d_off, d_cols, root, level, lanes, 256, ctl)
+                    except gq.GQError as e:
+                        log(f"[bench] bfs {name} {kind} lanes={lanes}: {e}")
+                        ok = False
+                        break
+                    e1.record()
+                    torch.cuda.synchronize()
+                    log(f"[bench] bfs {name} {kind} lanes={lanes} run {r}: "
+                        f"{e0.elapsed_time(e1):.2f} ms")
+                    if r:
+                        ms.append(e0.elapsed_time(e1))
+                if not ok or qa.check_error() != gq.GQ_OK:
+                    continue
+                match = bool(np.array_equal(level.cpu().numpy().view(np.uint32), exp))
+                med = float(np.median(ms))
+                key = f"{gq_name(kind)} lanes={lanes}"
+                res["runs"][key] = {"ms_median": med, "gteps": edges / (med * 1e-3) / 1e9,
+                                    "levels_match_oracle": match}
+                log(f"[bench] bfs {name} {key}: {med:.2f} ms, match={match}")
+                if match and (best is None or med < best[1]):
+                    best = (key, med)
+                qa.close()
+                qb.close()
+        if best:
+            res["best"] = {"config": best[0], "ms": best[1],
+                           "gteps": edges / (best[1] * 1e-3) / 1e9}
+        out[name] = res
+    return out
+
+
+def gq_name(kind):
+    return NAMES[kind]
+
+
+def bench_multi(gq, torch, kind="lfq", nq=256, ops=16, reps=5):
+    """Many independent queues: 256 queues, capacities 2^e with e uniform in
+    8..16 (seeded), each given one wavefront per 256 slots (at least one)
+    and 16 operations per lane, i.e. 4n operations per queue, in a 50/50 mix.
+    Compared: one launch for all queues, that launch replayed from a hipGraph,
+    and one launch per queue (the plain single-queue driver)."""
+    import workloads
+    rng = np.random.default_rng(workloads.run_seed(5, 0))
+    caps = [int(2 ** e) for e in rng.integers(8, 17, size=nq)]
+    lanes = [64 * max(1, c // 256) for c in caps]
+    pad = (-sum(lanes)) % 256
+    lanes[int(np.argmax(caps))] += pad
+    qs = [gq.Queue(kind, c, item_width=8, max_threads=l) for c, l in zip(caps, lanes)]
+    pre_items = []
+    for q, c in zip(qs, caps):
+        t = torch.arange(1, c // 2 + 1, dtype=torch.int64, device="cuda") | (0xFFFFFFFF << 32)
+        q.enqueue_batch(t)
+        pre_items.append(t)
+    m = gq.Multi(qs, lanes, block=256)
+    counts = torch.zeros(4 * nq, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    total_ops = sum(lanes) * ops
+    res = {"queues": nq, "capacities_log2_range": [8, 16], "total_lanes": sum(lanes),
+           "ops_per_step": total_ops, "kind": NAMES[kind]}
+    seed = workloads.run_seed(5, 10)
+    torch.cuda.synchronize()  # prefill ran on the default stream
+
+    def ok_count():
+        c = counts.cpu().numpy().reshape(-1, 4)
+        return int(c[:, 0].sum() + c[:, 1].sum())
+
+    with torch.cuda.stream(s):
+        m.run_mix(seed, ops, counts, stream=s)  # warmup
+        s.synchronize()
+        counts.zero_()
+        s.synchronize()
+        e0, e1 = _events(torch)
+        e0.record(s)
+        for r in range(reps):
+            m.run_mix(seed + r, ops, counts, stream=s)
+        e1.record(s)
+        s.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res["one_launch"] = {"ms_per_step": ms, "mops": ok_count() / reps / (ms * 1e-3) / 1e6}
+        counts.zero_()
+        m.capture(seed + 100, ops, counts, s)
+        m.replay(s)
+        s.synchronize()
+        counts.zero_()
+        s.synchronize()
+        e0, e1 = _events(torch)
+        e0.record(s)
+        for r in range(reps):
+            m.replay(s)
+        e1.record(s)
+        s.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res["graph_replay"] = {"ms_per_step": ms, "mops": ok_count() / reps / (ms * 1e-3) / 1e6}
+        counts.zero_()
+        s.synchronize()
+        e0, e1 = _events(torch)
+        e0.record(s)
+        for r in range(reps):
+            for i, q in enumerate(qs):
+                q.run_mix(seed + 1000 + r, lanes[i], ops, counts[4 * i:4 * i + 4], stream=s)
+        e1.record(s)
+        s.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res["launch_per_queue"] = {"ms_per_step": ms,
+                                   "mops": ok_count() / reps / (ms * 1e-3) / 1e6}
+    for q in qs:
+        if q.check_error() != gq.GQ_OK:
+            res["error"] = gq.status_str(q.check_error())
+    res["speedup_graph_vs_per_queue"] = (res["graph_replay"]["mops"] /
+                                         res["launch_per_queue"]["mops"])
+    m.close()
+    for q in qs:
+        q.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +312,8 @@ def main():
                     help="release/acquire payload hand-off instead of the atomic exchange")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-probes", action="store_true")
+    ap.add_argument("--no-bfs", action="store_true")
+    ap.add_argument("--no-multi", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -271,6 +443,15 @@ def main():
                         p["hbm_copy_gbs"] * 1e9 / BYTES_PER_OP)
         out["atomic_roofline"] = dict(p, bound_mops=bound_ops / 1e6, kernel=NAMES[dom],
                                       frac=dv["mops"] * 1e6 / bound_ops)
+    for q in queues.values():
+        q.close()
+    queues.clear()
+    torch.cuda.empty_cache()
+    if not args.no_multi:
+        out["batched_multi_queue"] = bench_multi(gq, torch)
+        log(f"[bench] multi: {out['batched_multi_queue']}")
+    if not args.no_bfs:
+        out["bfs"] = bench_bfs(gq, torch)
     if not args.no_cpu:
         replay, locked = cpu_baselines(base_seed, LANES)
         out["cpu_baseline"] = replay

@@ -129,6 +129,27 @@ __device__ __forceinline__ uint64_t wave_faa(uint64_t* ctr, uint64_t unit) {
   return base + (uint64_t)rank * unit;
 }
 
+// Largest value of v over the lanes active at this call (all of them get it).
+__device__ __forceinline__ uint64_t wave_max(uint64_t v) {
+  uint64_t m = active_mask(), mx = 0;
+  while (m) {
+    const int l = __ffsll((unsigned long long)m) - 1;
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
+    const uint64_t x = ((uint64_t)hi << 32) | lo;
+    mx = x > mx ? x : mx;
+    m &= m - 1;
+  }
+  return mx;
+}
+
+// WaveFAA on a signed counter stepping by -1 per lane: the lanes active at
+// this call receive old, old - 1, old - 2, ... in lane order (the values
+// per-lane decrements would return, in some order), with one atomic.
+__device__ __forceinline__ int64_t wave_fdec(int64_t* ctr) {
+  return (int64_t)wave_faa((uint64_t*)ctr, ~0ull);
+}
+
 // Wave sum of a per-lane value; every lane receives the total.
 __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
 #pragma unroll

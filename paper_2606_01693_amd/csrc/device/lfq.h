@@ -175,11 +175,20 @@ __device__ __forceinline__ uint32_t ring_deq(const Ring& r, uint32_t& cas_fail, 
     }
     const uint64_t t = ld(r.tail);
     if (t <= h + 1) {
-      catchup(r, t, h + 1);
-      faa(r.thr, (int64_t)-1);
+      // Every lane of the wavefront that is here catches Tail up to its h + 1
+      // and decrements Threshold.  Catching up to the largest h + 1 among
+      // them covers all of them, so one lane does it, and the decrements are
+      // one aggregated add: with thousands of lanes finding the queue empty
+      // together this avoids a storm of CAS retries on Tail.
+      const uint64_t target = wave_max(h + 1);
+      const uint64_t mask = active_mask();
+      if (lane_rank(mask) == 0) {
+        catchup(r, ld(r.tail), target);
+        faa(r.thr, -(int64_t)__popcll(mask));
+      }
       return BOT;
     }
-    if (faa(r.thr, (int64_t)-1) <= 0) return BOT;
+    if (wave_fdec(r.thr) <= 0) return BOT;
   }
 }
 

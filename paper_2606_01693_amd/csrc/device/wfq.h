@@ -220,11 +220,17 @@ __device__ __forceinline__ uint32_t try_deq(const WRing& r, uint64_t h, uint32_t
   }
   const uint64_t t = g_ctr(ld(r.g.tail));
   if (t <= h + 1) {
-    catchup(r, h + 1);
-    faa(r.g.thr, (int64_t)-1);
+    // one catch-up to the wavefront's largest h + 1 and one aggregated
+    // Threshold decrement for all lanes here (as in the G-LFQ fast path)
+    const uint64_t target = wave_max(h + 1);
+    const uint64_t mask = active_mask();
+    if (lane_rank(mask) == 0) {
+      catchup(r, target);
+      faa(r.g.thr, -(int64_t)__popcll(mask));
+    }
     return BOT;
   }
-  if (faa(r.g.thr, (int64_t)-1) <= 0) return BOT;
+  if (wave_fdec(r.g.thr) <= 0) return BOT;
   return DEQ_RETRY;
 }
 
