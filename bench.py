@@ -300,6 +300,89 @@ def bench_multi(gq, torch, kind="lfq", nq=256, ops=16, reps=5):
     return res
 
 
+def bench_ticket_ablation(gq, torch, kinds, seed, args, reps=3):
+    """The step's kernel with each ticket grouping: 64 lanes (every wavefront
+    takes its own tickets, WaveFAA alone) up to 1024 lanes (one FAA per
+    counter per workgroup).  Same workload; median kernel time of `reps`
+    launches after one warmup."""
+    out = {}
+    for kind in kinds:
+        for tg in (64, 256, 1024):
+            q = gq.Queue(kind, CAP, item_width=ITEM_BYTES, max_threads=LANES,
+                         slot_mode=args.slot_mode, fenced=args.fenced,
+                         ymc_pool_cells=(1 << 28) if kind == "ymc" else 0, ticket_group=tg)
+            pre = torch.arange(1, CAP // 2 + 1, dtype=torch.int64, device="cuda") | (0xFFFFFFFF << 32)
+            q.enqueue_batch(pre)
+            counts = torch.zeros(4, dtype=torch.int64, device="cuda")
+            ms = []
+            for r in range(reps + 1):
+                e0, e1 = _events(torch)
+                e0.record()
+                q.run_mix(seed + 500 + r, LANES, OPS_PER_LANE, counts)
+                e1.record()
+                torch.cuda.synchronize()
+                if r:
+                    ms.append(e0.elapsed_time(e1))
+            c = counts.cpu().tolist()
+            ok = (c[0] + c[1]) / (reps + 1)
+            med = float(np.median(ms))
+            assert q.check_error() == gq.GQ_OK
+            out[f"{NAMES[kind]} group={tg}"] = {"kernel_ms": med,
+                                                "mops": ok / (med * 1e-3) / 1e6}
+            log(f"[bench] tickets {NAMES[kind]} group={tg}: {med:.2f} ms, "
+                f"{ok / (med * 1e-3) / 1e6:.0f} Mops/s")
+            q.close()
+            del pre
+            torch.cuda.empty_cache()
+    return out
+
+
+def bench_c3(gq, torch, kinds=("lfq", "ymc"), items=1 << 23, cap=1 << 16, waves=1024):
+    """Imbalanced producer/consumer runs: 1024 wavefronts of which the seed
+    makes 128, 512 or 896 producers; a lane is active in a round with
+    probability 1, 1/2 or 1/64; producers retry on FULL, consumers on EMPTY,
+    until 2^23 items went through.  Mops/s counts successful operations
+    (2 x items) over the kernel time; conservation is checked through the
+    driver's multiset checksums.  G-WFQ is left out at this size: with 7:1
+    polling consumers its slow path does not finish in a usable time (see the
+    design notes)."""
+    import workloads
+    lanes = waves * 64
+    out = {}
+    for kind in kinds:
+        q = gq.Queue(kind, cap, item_width=8, max_threads=lanes,
+                     ymc_pool_cells=(1 << 28) if kind == "ymc" else 0)
+        for prod in (128, 512, 896):
+            for l2p in (0, 1, 6):
+                seed = workloads.run_seed(3, prod + l2p)
+                mask = workloads.producer_waves(seed, waves, prod)
+                role = torch.tensor(np.repeat(np.where(mask, 0, 1), 64).astype(np.uint8),
+                                    device="cuda")
+                quota = -(-items // (prod * 64))
+                target = quota * prod * 64
+                counts = torch.zeros(8, dtype=torch.int64, device="cuda")
+                q.reset()
+                torch.cuda.synchronize()
+                e0, e1 = _events(torch)
+                e0.record()
+                q.run_prodcons(seed, lanes, 256, role, quota, target, l2p, 0, counts,
+                               max_rounds=1 << 30, time_limit_ms=30000)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1)
+                c = counts.cpu().numpy().view(np.uint64)
+                ok = bool(c[0] == target and c[1] == target and c[4] == c[6] and c[5] == c[7]
+                          and q.check_error() == gq.GQ_OK)
+                key = f"{NAMES[kind]} {prod}:{waves - prod} p=2^-{l2p}"
+                out[key] = {"ms": ms, "mops": 2 * target / (ms * 1e-3) / 1e6,
+                            "full_retries": int(c[2]), "empty_retries": int(c[3]),
+                            "conserved": ok}
+                log(f"[bench] c3 {key}: {ms:.2f} ms, {out[key]['mops']:.0f} Mops/s, ok={ok}")
+        q.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,6 +397,10 @@ def main():
     ap.add_argument("--no-probes", action="store_true")
     ap.add_argument("--no-bfs", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
+    ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--ticket-group", type=int, default=0,
+                    help="lanes per ticket FAA in the step (64 = one wavefront; 0 = 1024)")
+    ap.add_argument("--no-ablation", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -335,7 +422,8 @@ def main():
         # between steps): 2^29 cells of 32 B.
         q = gq.Queue(kind, CAP, item_width=ITEM_BYTES, max_threads=LANES,
                      slot_mode=args.slot_mode, fenced=args.fenced,
-                     ymc_pool_cells=(1 << 29) if kind == "ymc" else 0)
+                     ymc_pool_cells=(1 << 29) if kind == "ymc" else 0,
+                     ticket_group=args.ticket_group)
         pre = torch.arange(1, CAP // 2 + 1, dtype=torch.int64, device="cuda") | (0xFFFFFFFF << 32)
         q.enqueue_batch(pre)
         queues[kind] = q
@@ -414,7 +502,8 @@ def main():
                         "step runs that batch through each queue variant in turn: "
                         + ", ".join(NAMES[k] for k in kinds)
                         + f"; slots={args.slot_mode}, hand-off="
-                        + ("fenced" if args.fenced else "atomic"),
+                        + ("fenced" if args.fenced else "atomic")
+                        + f", first tickets per {args.ticket_group or 1024} lanes",
             "capacity": CAP, "lanes": LANES, "ops_per_lane": OPS_PER_LANE,
             "variants": kinds, "parallelism": "single GPU",
         },
@@ -447,9 +536,13 @@ def main():
         q.close()
     queues.clear()
     torch.cuda.empty_cache()
+    if not args.no_ablation:
+        out["ticket_ablation"] = bench_ticket_ablation(gq, torch, kinds, base_seed, args)
     if not args.no_multi:
         out["batched_multi_queue"] = bench_multi(gq, torch)
         log(f"[bench] multi: {out['batched_multi_queue']}")
+    if not args.no_c3:
+        out["imbalanced_prodcons"] = bench_c3(gq, torch)
     if not args.no_bfs:
         out["bfs"] = bench_bfs(gq, torch)
     if not args.no_cpu:

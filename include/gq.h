@@ -77,13 +77,18 @@ typedef enum { GQ_SLOTS_REMAP = 0, GQ_SLOTS_PADDED = 1, GQ_SLOTS_LINEAR = 2 } gq
 typedef struct gq_options {
     uint32_t slot_mode;        /* gq_slot_mode (opts == NULL: GQ_SLOTS_LINEAR) */
     uint32_t flags;            /* GQ_OPT_* bits                               */
-    uint64_t ymc_pool_cells;   /* G-WFQ-YMC pool size; 0 = 2^27 cells or
-                                  16 * capacity, whichever is larger          */
+    uint64_t ymc_pool_cells;   /* G-WFQ-YMC pool size; 0 = 2^20 cells or
+                                  64 * capacity, whichever is larger          */
     uint32_t wfq_patience_enq; /* fast-path attempts before the slow path     */
     uint32_t wfq_patience_deq;
     uint32_t wfq_help_delay;   /* D: operations between peer-record checks,
                                   1..4095                                     */
-    uint32_t reserved;
+    uint32_t ticket_group;     /* lanes whose first tickets the library's
+                                  workgroup-uniform drivers (gq_run_mix,
+                                  batches) take with one fetch-and-add per
+                                  counter: 64 = one wavefront (WaveFAA
+                                  alone), 128..1024 = a workgroup of that
+                                  many lanes (power of two); 0 = 1024      */
 } gq_options;
 
 /* ---- device view ---------------------------------------------------------
@@ -119,7 +124,7 @@ typedef struct gq_dev {
     uint32_t patience_enq;     /* G-WFQ fast-path attempts                    */
     uint32_t patience_deq;
     uint32_t help_delay;       /* G-WFQ help delay D                          */
-    uint32_t pad1;
+    uint32_t group_lanes;      /* gq_options.ticket_group (resolved)          */
     uint32_t *help_ctr;        /* G-WFQ per-lane <next peer:20 | ops:12>      */
 } gq_dev;
 

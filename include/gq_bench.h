@@ -99,12 +99,17 @@ gq_status gq_run_balanced(gq_queue *q, uint32_t lanes, uint32_t rounds, uint64_t
  * other, so all lanes must be co-resident (GQ_ERR_RESIDENCY otherwise).
  * jitter > 0 adds a seeded pause of up to `jitter` sleep units per round.
  * max_rounds bounds every lane's loop; exceeding it latches GQ_ERR_DEVICE.
- * d_counts[4] += {ok_enq, ok_deq, full, empty}.                               */
+ * time_limit_ms (0 = none) bounds the run's duration on the GPU clock: a lane
+ * past it stops and latches GQ_ERR_DEVICE (a bounded wait, not a result).
+ * d_counts[8] += {ok_enq, ok_deq, full, empty, S1_deq, S2_deq, S1_enq,
+ * S2_enq}, where S1 and S2 are the wrapping (mod 2^64) sums of v and v * v
+ * over the items v successfully dequeued (deq) or enqueued (enq): multiset
+ * checksums that let a caller verify conservation without a history.        */
 gq_status gq_run_prodcons(gq_queue *q, uint64_t seed, uint32_t lanes, uint32_t block,
                           const uint8_t *d_lane_role, uint32_t items_per_producer,
                           uint64_t target, uint32_t log2_inv_p, uint32_t token_mode,
-                          uint32_t jitter, uint64_t max_rounds, uint64_t *d_counts,
-                          const gq_history *hist, void *stream);
+                          uint32_t jitter, uint64_t max_rounds, uint32_t time_limit_ms,
+                          uint64_t *d_counts, const gq_history *hist, void *stream);
 
 /* Scripted run for small linearizability tests: lane g (< lanes <= 1024)
  * executes n_ops[g] operations from ops[g * max_ops ...] (0 enqueue,

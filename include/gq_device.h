@@ -63,6 +63,31 @@ __device__ __forceinline__ int gq_dequeue_k(const gq_dev& q, uint64_t* item, uin
   }
 }
 
+/* Workgroup-uniform form: every thread of the workgroup calls
+ * gq_group_op_k together (uniform control flow, blockDim a multiple of 64
+ * and at most 1024), each with its own role: gq::ROLE_ENQ (enqueue `item`),
+ * gq::ROLE_DEQ (dequeue into `item`) or gq::ROLE_NONE.  The first ticket of
+ * each inner operation is taken with one fetch-and-add per counter for the
+ * whole workgroup (Lemma 1's aggregation at workgroup scale); the operation
+ * is otherwise the same linearizable enqueue or dequeue as above.  `lds` is
+ * one __shared__ gq::GroupLds per workgroup and `par` a per-thread word that
+ * starts at 0 and is passed to every call.  Returns the lane's status
+ * (GQ_OK for ROLE_NONE).  Contains barriers: never call it from divergent
+ * code.                                                                      */
+template <int KIND>
+__device__ __forceinline__ int gq_group_op_k(const gq_dev& q, int role, uint64_t& item,
+                                             uint32_t tid, uint32_t& cas_fail, gq::GroupLds& lds,
+                                             uint32_t& par) {
+  if constexpr (KIND == GQ_LFQ) {
+    (void)tid;
+    return gq::lfq::group_op(q, role, item, cas_fail, lds, par);
+  } else if constexpr (KIND == GQ_WFQ) {
+    return gq::wfq::group_op(q, role, item, tid, cas_fail, lds, par);
+  } else {
+    return gq::ymc::group_op(q, role, item, tid, cas_fail, lds, par);
+  }
+}
+
 __device__ __forceinline__ int gq_enqueue(const gq_dev& q, uint64_t item, uint32_t tid) {
   uint32_t cf = 0;
   switch (q.kind) {

@@ -31,6 +31,7 @@ EXPORTS = (
     "gq_run_script", "gq_probe_faa", "gq_probe_cas", "gq_probe_copy", "gq_probe_fence",
     "gq_resident_blocks", "gq_device_info", "gq_multi_create", "gq_multi_run_mix",
     "gq_multi_capture", "gq_multi_replay", "gq_multi_destroy", "gq_bfs",
+    "gq_serve_create", "gq_serve_run", "gq_serve_job_bytes", "gq_serve_destroy",
 )
 
 
@@ -48,11 +49,11 @@ class _Options(ctypes.Structure):
     _fields_ = [("slot_mode", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("ymc_pool_cells", ctypes.c_uint64), ("wfq_patience_enq", ctypes.c_uint32),
                 ("wfq_patience_deq", ctypes.c_uint32), ("wfq_help_delay", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("ticket_group", ctypes.c_uint32)]
 
 
 def make_options(slot_mode="linear", fenced=False, ymc_pool_cells=0, patience=None,
-                 help_delay=None) -> _Options:
+                 help_delay=None, ticket_group=0) -> _Options:
     flags = GQ_OPT_FENCED if fenced else 0
     pe, pd, hd = 16, 64, 64
     if patience is not None or help_delay is not None:
@@ -61,7 +62,7 @@ def make_options(slot_mode="linear", fenced=False, ymc_pool_cells=0, patience=No
             pe, pd = (patience, patience) if isinstance(patience, int) else patience
         if help_delay is not None:
             hd = help_delay
-    return _Options(SLOT_MODES[slot_mode], flags, ymc_pool_cells, pe, pd, hd, 0)
+    return _Options(SLOT_MODES[slot_mode], flags, ymc_pool_cells, pe, pd, hd, ticket_group)
 
 
 class _Stats(ctypes.Structure):
@@ -92,7 +93,7 @@ class _DevView(ctypes.Structure):
                 ("ymc_pool_cells", ctypes.c_uint64), ("ymc_ctr", ctypes.c_void_p),
                 ("ymc_handles", ctypes.c_void_p), ("patience_enq", ctypes.c_uint32),
                 ("patience_deq", ctypes.c_uint32), ("help_delay", ctypes.c_uint32),
-                ("pad1", ctypes.c_uint32), ("help_ctr", ctypes.c_void_p)]
+                ("group_lanes", ctypes.c_uint32), ("help_ctr", ctypes.c_void_p)]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -118,7 +119,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gq_check_error": [P, P],
         "gq_run_mix": [P, U64, U32, U32, P, P, P],
         "gq_run_balanced": [P, U32, U32, P, P, P],
-        "gq_run_prodcons": [P, U64, U32, U32, P, U32, U64, U32, U32, U32, U64, P, P, P],
+        "gq_run_prodcons": [P, U64, U32, U32, P, U32, U64, U32, U32, U32, U64, U32, P, P, P],
         "gq_run_script": [P, U32, U32, P, P, P, P, U32, P, P],
         "gq_probe_faa": [P, U32, U32, U32, U32, U32, P],
         "gq_probe_cas": [P, U64, U32, U32, U32, P],
@@ -132,6 +133,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gq_multi_replay": [P, P],
         "gq_multi_destroy": [P],
         "gq_bfs": [P, P, P, P, U32, U32, P, U32, U32, P, P],
+        "gq_serve_create": [U32, U32, I32, U64, U32, U32, P],
+        "gq_serve_run": [P, U32, P, P, U32, P],
+        "gq_serve_job_bytes": [P, U32, U64, P],
+        "gq_serve_destroy": [P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -172,6 +177,17 @@ def _stream(stream=None):
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need_words(counts, words: int, what: str):
+    """Device buffers are plain pointers at the C ABI: check their size here."""
+    if counts.numel() * counts.element_size() < 8 * words:
+        raise ValueError(f"{what} needs a counts buffer of at least {words} int64 words")
+
+
+def _need_hist(hist, lanes: int, what: str):
+    if hist is not None and hist.lanes < lanes:
+        raise ValueError(f"{what}: history holds {hist.lanes} lanes, run uses {lanes}")
 
 
 def _ptr(t) -> ctypes.c_void_p:
@@ -241,11 +257,12 @@ class Queue:
 
     def __init__(self, kind: str, capacity: int, item_width: int = 8, max_threads: int = 1,
                  slot_mode: str = "linear", ymc_pool_cells: int = 0, fenced: bool = False,
-                 patience=None, help_delay=None):
+                 patience=None, help_delay=None, ticket_group: int = 0):
         torch = _torch()
         self.kind, self.capacity, self.item_width = kind, capacity, item_width
         self.max_threads = max_threads
-        self._opts = make_options(slot_mode, fenced, ymc_pool_cells, patience, help_delay)
+        self._opts = make_options(slot_mode, fenced, ymc_pool_cells, patience, help_delay,
+                                  ticket_group)
         o = self._opts
         out = ctypes.c_uint64(0)
         _check(lib().gq_required_bytes(KINDS[kind], capacity, item_width, max_threads,
@@ -305,12 +322,16 @@ class Queue:
     # ---- workload drivers --------------------------------------------------
     def run_mix(self, seed: int, lanes: int, ops_per_lane: int, counts, hist: History = None,
                 stream=None):
+        _need_words(counts, 4, "run_mix")
+        _need_hist(hist, lanes, "run_mix")
         hc = hist.c() if hist is not None else None
         _check(lib().gq_run_mix(self._h, seed, lanes, ops_per_lane, _ptr(counts),
                                 ctypes.byref(hc) if hc is not None else None, _stream(stream)),
                "gq_run_mix")
 
     def run_balanced(self, lanes: int, rounds: int, counts, hist: History = None, stream=None):
+        _need_words(counts, 4, "run_balanced")
+        _need_hist(hist, lanes, "run_balanced")
         hc = hist.c() if hist is not None else None
         _check(lib().gq_run_balanced(self._h, lanes, rounds, _ptr(counts),
                                      ctypes.byref(hc) if hc is not None else None,
@@ -318,11 +339,16 @@ class Queue:
 
     def run_prodcons(self, seed: int, lanes: int, block: int, lane_role, items_per_producer: int,
                      target: int, log2_inv_p: int, token_mode: int, counts, hist: History = None,
-                     jitter: int = 0, max_rounds: int = 1 << 26, stream=None):
+                     jitter: int = 0, max_rounds: int = 1 << 26, time_limit_ms: int = 60000,
+                     stream=None):
+        _need_words(counts, 8, "run_prodcons")
+        _need_hist(hist, lanes, "run_prodcons")
+        if lane_role.numel() < lanes:
+            raise ValueError("lane_role must hold one entry per lane")
         hc = hist.c() if hist is not None else None
         _check(lib().gq_run_prodcons(self._h, seed, lanes, block, _ptr(lane_role),
                                      items_per_producer, target, log2_inv_p, token_mode, jitter,
-                                     max_rounds, _ptr(counts),
+                                     max_rounds, time_limit_ms, _ptr(counts),
                                      ctypes.byref(hc) if hc is not None else None,
                                      _stream(stream)), "gq_run_prodcons")
 
@@ -384,12 +410,15 @@ class Multi:
         self._h = h
 
     def run_mix(self, seed: int, ops_per_lane: int, counts, hist: History = None, stream=None):
+        _need_words(counts, 4 * len(self.queues), "Multi.run_mix")
+        _need_hist(hist, sum(self.lanes), "Multi.run_mix")
         hc = hist.c() if hist is not None else None
         _check(lib().gq_multi_run_mix(self._h, seed, ops_per_lane, _ptr(counts),
                                       ctypes.byref(hc) if hc is not None else None,
                                       _stream(stream)), "gq_multi_run_mix")
 
     def capture(self, seed: int, ops_per_lane: int, counts, stream):
+        _need_words(counts, 4 * len(self.queues), "Multi.capture")
         _check(lib().gq_multi_capture(self._h, seed, ops_per_lane, _ptr(counts), _stream(stream)),
                "gq_multi_capture")
 
@@ -411,5 +440,96 @@ class Multi:
 def bfs(qa: Queue, qb: Queue, offsets, cols, root: int, level, lanes: int, block: int, ctl,
         stream=None):
     """Launch the queue-driven BFS; offsets/cols/level/ctl are CUDA tensors."""
+    nv = offsets.numel() - 1
+    if level.numel() < nv or cols.numel() < 1 or ctl.numel() * ctl.element_size() < 1024:
+        raise ValueError("bfs: level must hold nv entries, ctl at least 1 KiB")
     _check(lib().gq_bfs(qa.handle, qb.handle, _ptr(offsets), _ptr(cols), offsets.numel() - 1,
                         root, _ptr(level), lanes, block, _ptr(ctl), _stream(stream)), "gq_bfs")
+
+
+# ---------------------------------------------------------------------------
+# Serving (include/gq_serve.h)
+# ---------------------------------------------------------------------------
+class _ServeRequest(ctypes.Structure):
+    _fields_ = [("d_offsets", ctypes.c_void_p), ("d_cols", ctypes.c_void_p),
+                ("d_levels_out", ctypes.c_void_p), ("nnz", ctypes.c_uint64),
+                ("nv", ctypes.c_uint32), ("root", ctypes.c_uint32)]
+
+
+class _ServeResult(ctypes.Structure):
+    _fields_ = [("arrival_ns", ctypes.c_int64), ("admit_ns", ctypes.c_int64),
+                ("done_ns", ctypes.c_int64), ("device_ns", ctypes.c_int64),
+                ("level_hash", ctypes.c_uint64), ("levels", ctypes.c_uint64),
+                ("scanned", ctypes.c_uint64), ("job_bytes", ctypes.c_uint64),
+                ("team", ctypes.c_uint32), ("status", ctypes.c_int32)]
+
+
+SERVE_HASH_SEED = 0x5EED1E7E15
+
+
+class Server:
+    """A persistent serving kernel (gq_serve_create .. gq_serve_destroy).
+
+    While it exists it occupies the GPU: do not call torch.cuda.synchronize()
+    (a device-wide wait) until close(); put the graphs on the device first.
+    Graph tensors passed to run() must stay alive until run() returns."""
+
+    def __init__(self, teams: int, team_lanes: int = 1024, kind: str = "lfq",
+                 budget_bytes: int = 16 << 30, ring_slots: int = 1024,
+                 idle_timeout_ms: int = 0):
+        h = ctypes.c_void_p(0)
+        _check(lib().gq_serve_create(teams, team_lanes, KINDS[kind], budget_bytes, ring_slots,
+                                     idle_timeout_ms, ctypes.byref(h)), "gq_serve_create")
+        self._h = h
+        self.teams, self.team_lanes, self.kind = teams, team_lanes, kind
+        self.budget_bytes, self.ring_slots = budget_bytes, ring_slots
+
+    def job_bytes(self, nv: int, nnz: int) -> int:
+        out = ctypes.c_uint64(0)
+        _check(lib().gq_serve_job_bytes(self._h, nv, nnz, ctypes.byref(out)),
+               "gq_serve_job_bytes")
+        return int(out.value)
+
+    def run(self, requests, arrival_ns, max_inflight: int = None):
+        """requests: sequence of (offsets, cols, root) or (offsets, cols, root,
+        levels_out) with int32 CUDA tensors (levels_out: nv entries, receives
+        the job's levels).  arrival_ns: non-decreasing schedule (ns from the
+        call).  Returns a dict of numpy arrays, one entry per request."""
+        n = len(requests)
+        reqs = (_ServeRequest * max(1, n))()
+        for i, rq in enumerate(requests):
+            off, cols, root = rq[:3]
+            out_t = rq[3] if len(rq) > 3 else None
+            nv = off.numel() - 1
+            if out_t is not None and out_t.numel() < nv:
+                raise ValueError("levels_out must hold nv entries")
+            reqs[i] = _ServeRequest(off.data_ptr(), cols.data_ptr(),
+                                    out_t.data_ptr() if out_t is not None else None,
+                                    cols.numel(), nv, int(root))
+        arr = np.ascontiguousarray(np.asarray(arrival_ns, dtype=np.int64))
+        if len(arr) != n:
+            raise ValueError("one arrival time per request")
+        res = (_ServeResult * max(1, n))()
+        mi = self.ring_slots if max_inflight is None else max_inflight
+        _check(lib().gq_serve_run(self._h, n, reqs, arr.ctypes.data, mi, res), "gq_serve_run")
+        out = {f[0]: np.array([getattr(res[i], f[0]) for i in range(n)])
+               for f in _ServeResult._fields_}
+        out["level_hash"] = out["level_hash"].astype(np.uint64)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            _check(lib().gq_serve_destroy(h), "gq_serve_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -150,6 +150,68 @@ __device__ __forceinline__ int64_t wave_fdec(int64_t* ctr) {
   return (int64_t)wave_faa((uint64_t*)ctr, ~0ull);
 }
 
+// ---------------------------------------------------------------------------
+// Workgroup-aggregated tickets.  Lemma 1's argument does not depend on the
+// lanes sharing a fetch-and-add being one wavefront: any set of requests that
+// are all pending when one FAA of their count is performed can take
+// base, base + 1, ... in a fixed order, exactly as if each had performed its
+// own FAA at that instant.  group_ticket applies it to a whole workgroup
+// (up to 16 wavefronts), so each ticket counter sees one FAA per workgroup
+// instead of one per wavefront.  Every thread of the workgroup must call it
+// with uniform control flow (it contains two barriers).
+//
+// Two counters are served per call (an operation mix takes tickets on two
+// different counters in the same phase); a lane requests from at most one of
+// them (w0 and w1 exclusive).  `unit` is the FAA step per ticket (packed
+// counters).  The result is the counter value the lane's own FAA would have
+// returned, or GROUP_NONE if the lane requested nothing.
+// ---------------------------------------------------------------------------
+constexpr uint64_t GROUP_NONE = ~0ull;
+constexpr uint32_t GROUP_MAX_WAVES = 16;
+
+struct GroupLds {
+  uint64_t base[2][GROUP_MAX_WAVES][2];
+  uint32_t cnt[2][GROUP_MAX_WAVES][2];
+};
+
+// `par` alternates the LDS buffers between consecutive calls: a wavefront
+// may enter call i + 1 while a slower one still reads call i's bases, but it
+// cannot reach call i + 2 before every wavefront has passed call i + 1's first
+// barrier, i.e. finished reading call i.
+__device__ __forceinline__ uint64_t group_ticket(GroupLds& s, uint32_t& par, uint64_t* c0,
+                                                 uint64_t u0, bool w0, uint64_t* c1, uint64_t u1,
+                                                 bool w1) {
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t nw = blockDim.x >> 6;
+  const uint64_t m0 = __ballot(w0);
+  const uint64_t m1 = __ballot(w1);
+  const uint32_t p = par;
+  par ^= 1u;
+  if ((threadIdx.x & 63) == 0) {
+    s.cnt[p][wave][0] = (uint32_t)__popcll(m0);
+    s.cnt[p][wave][1] = (uint32_t)__popcll(m1);
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const uint32_t j = threadIdx.x;
+    uint64_t tot = 0;
+    for (uint32_t w = 0; w < nw; w++) tot += s.cnt[p][w][j];
+    const uint64_t u = j ? u1 : u0;
+    uint64_t b = tot ? faa(j ? c1 : c0, tot * u) : 0;
+    for (uint32_t w = 0; w < nw; w++) {
+      s.base[p][w][j] = b;
+      b += (uint64_t)s.cnt[p][w][j] * u;
+    }
+  }
+  __syncthreads();
+  if (w0) return s.base[p][wave][0] + (uint64_t)lane_rank(m0) * u0;
+  if (w1) return s.base[p][wave][1] + (uint64_t)lane_rank(m1) * u1;
+  return GROUP_NONE;
+}
+
+// Operation roles of a workgroup-uniform call.
+enum GroupRole { ROLE_ENQ = 0, ROLE_DEQ = 1, ROLE_NONE = 2 };
+
 // Wave sum of a per-lane value; every lane receives the total.
 __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
 #pragma unroll

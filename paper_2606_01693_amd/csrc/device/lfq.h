@@ -106,16 +106,24 @@ __device__ __forceinline__ void catchup(const Ring& r, uint64_t t, uint64_t h) {
 // Inner enqueue of index `idx` (Algorithm 1, TryEnq, retried until success).
 // RELEASE makes the install CAS an agent-scope release (fenced hand-off).  An index ring never holds more than
 // n indices in 2n slots, so the retry loop ends (lock-freedom, Section III-B).
+// `first`: a Tail ticket already reserved for this operation (workgroup
+// aggregation), used for the first attempt; GROUP_NONE to take one here.
 template <bool RELEASE>
 __device__ __forceinline__ bool ring_enq(const Ring& r, uint32_t idx, uint32_t& cas_fail,
-                                         uint64_t* err) {
+                                         uint64_t* err, uint64_t first = GROUP_NONE) {
   bool done = false;
   for (uint32_t spin = 0; !done; spin++) {
     if (spin >= SPIN_LIMIT) {
       latch_error(err, (uint64_t)(-GQ_ERR_DEVICE));
       return false;
     }
-    const uint64_t t = wave_faa(r.tail, 1);
+    uint64_t t;
+    if (first != GROUP_NONE) {
+      t = first;
+      first = GROUP_NONE;
+    } else {
+      t = wave_faa(r.tail, 1);
+    }
     const uint32_t c = r.cycle_of(t);
     uint64_t* p = r.at(r.slot_of(t));
     uint64_t e = ld(p);
@@ -142,15 +150,27 @@ __device__ __forceinline__ bool ring_enq(const Ring& r, uint32_t idx, uint32_t& 
 // acquire (fenced hand-off).  Consume is an atomic XOR that turns
 // the index field into BOTC and leaves Cycle/Safe alone; between install and
 // consume only Safe can change, so the XOR is exact.
+//
+// `first`: a Head ticket already reserved for this operation (workgroup
+// aggregation; the caller checked Threshold before reserving it).  It is
+// always used: a Head ticket that no dequeuer visits could let an enqueuer
+// install behind Head, where no later ticket reaches the item.
 template <bool ACQUIRE>
-__device__ __forceinline__ uint32_t ring_deq(const Ring& r, uint32_t& cas_fail, uint64_t* err) {
+__device__ __forceinline__ uint32_t ring_deq(const Ring& r, uint32_t& cas_fail, uint64_t* err,
+                                             uint64_t first = GROUP_NONE) {
   for (uint32_t spin = 0;; spin++) {
     if (spin >= SPIN_LIMIT) {
       latch_error(err, (uint64_t)(-GQ_ERR_DEVICE));
       return BOT;
     }
-    if (ld(r.thr) < 0) return BOT;
-    const uint64_t h = wave_faa(r.head, 1);
+    uint64_t h;
+    if (first != GROUP_NONE) {
+      h = first;
+      first = GROUP_NONE;
+    } else {
+      if (ld(r.thr) < 0) return BOT;
+      h = wave_faa(r.head, 1);
+    }
     const uint32_t c = r.cycle_of(h);
     uint64_t* p = r.at(r.slot_of(h));
     uint64_t e = ld(p);
@@ -262,6 +282,50 @@ __device__ __forceinline__ int dequeue_impl(const gq_dev& q, uint64_t* item, uin
   *item = payload_get<FENCED>(q, idx);
   ring_enq<FENCED>(fq, idx, cas_fail, q.err);
   return GQ_OK;
+}
+
+// ---- workgroup-uniform form ----------------------------------------------
+// Every thread of the workgroup calls group_op together, each with its own
+// role (enqueue `item`, dequeue into `item`, or nothing).  The first ticket of
+// each inner operation comes from one FAA per counter per workgroup
+// (group_ticket); retries take WaveFAA tickets as usual.  Phase A takes an
+// index (fq.Head for enqueues, aq.Head for dequeues), phase B passes it on
+// (aq.Tail for enqueues, fq.Tail for dequeues).  Returns the lane's status
+// (GQ_OK for ROLE_NONE).
+template <bool FENCED>
+__device__ __forceinline__ int group_op_impl(const gq_dev& q, int role, uint64_t& item,
+                                             uint32_t& cas_fail, GroupLds& s, uint32_t& par) {
+  const Ring fq = make_ring(q.fq, q);
+  const Ring aq = make_ring(q.aq, q);
+  // The Threshold test of a dequeue precedes its ticket, as in ring_deq.
+  const bool wf = role == ROLE_ENQ && ld(fq.thr) >= 0;
+  const bool wa = role == ROLE_DEQ && ld(aq.thr) >= 0;
+  uint64_t t = group_ticket(s, par, fq.head, 1, wf, aq.head, 1, wa);
+  uint32_t idx = BOT;
+  if (wf) idx = ring_deq<false>(fq, cas_fail, q.err, t);
+  else if (wa) idx = ring_deq<FENCED>(aq, cas_fail, q.err, t);
+  if (idx != BOT && idx >= q.capacity) {  // never taken: guards the payload array
+    latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
+    idx = BOT;
+  }
+  int st = role == ROLE_ENQ ? GQ_FULL : role == ROLE_DEQ ? GQ_EMPTY : GQ_OK;
+  if (idx != BOT) {
+    if (role == ROLE_ENQ) payload_put<FENCED>(q, idx, item);
+    else item = payload_get<FENCED>(q, idx);
+    st = GQ_OK;
+  }
+  const bool we = role == ROLE_ENQ && idx != BOT;
+  const bool wd = role == ROLE_DEQ && idx != BOT;
+  t = group_ticket(s, par, aq.tail, 1, we, fq.tail, 1, wd);
+  if (we) ring_enq<FENCED>(aq, idx, cas_fail, q.err, t);
+  else if (wd) ring_enq<FENCED>(fq, idx, cas_fail, q.err, t);
+  return st;
+}
+
+__device__ __forceinline__ int group_op(const gq_dev& q, int role, uint64_t& item,
+                                        uint32_t& cas_fail, GroupLds& s, uint32_t& par) {
+  return (q.flags & GQ_OPT_FENCED) ? group_op_impl<true>(q, role, item, cas_fail, s, par)
+                                   : group_op_impl<false>(q, role, item, cas_fail, s, par);
 }
 
 __device__ __forceinline__ int enqueue(const gq_dev& q, uint64_t item, uint32_t& cas_fail) {

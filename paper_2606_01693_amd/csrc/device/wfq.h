@@ -424,8 +424,12 @@ __device__ __forceinline__ void unpublish(Rec* R, bool is_enq, uint64_t seq) {
 }
 
 // Help lane p's pending request on ring r, if any (the help step, D = help delay).
+// A relaxed look at the request word comes first: with no request pending
+// (the common case) the check costs one load and no cache invalidation; a
+// request published after this look is simply helped on a later visit.
 __device__ __forceinline__ void help_peer(const WRing& r, uint32_t p) {
   Rec* R = &r.rec[p];
+  if (!(ld(&R->req) & 1)) return;
   const uint64_t q1 = ld_acq(&R->req);
   if (!(q1 & 1)) return;
   const uint64_t init = ld_acq(&R->init);
@@ -458,11 +462,17 @@ __device__ __forceinline__ void help_check(const gq_dev& q, uint32_t tid) {
 }
 
 // Inner enqueue of idx: fast path up to patience_enq attempts, then the slow path.
+// `first`: a Tail ticket already reserved for this operation (workgroup
+// aggregation), tried before the fast-path loop; NO_TICKET if none.
 template <bool RELEASE>
 __device__ __forceinline__ void ring_enq(const WRing& r, const gq_dev& q, uint32_t tid, uint32_t idx,
-                                         uint32_t& cf) {
+                                         uint32_t& cf, uint64_t first = NO_TICKET) {
   uint64_t last = NO_TICKET;
-  for (uint32_t a = 0; a < q.patience_enq; a++) {
+  if (first != NO_TICKET) {
+    if (try_enq<RELEASE>(r, first, idx, cf)) return;
+    last = first;
+  }
+  for (uint32_t a = first != NO_TICKET ? 1u : 0u; a < q.patience_enq; a++) {
     const uint64_t t = ticket(wave_faa(r.g.tail, UNIT));
     if (try_enq<RELEASE>(r, t, idx, cf)) return;
     last = t;
@@ -487,11 +497,19 @@ __device__ __forceinline__ void ring_enq(const WRing& r, const gq_dev& q, uint32
 }
 
 // Inner dequeue: returns an index or BOT (EMPTY).
+// `first`: a Head ticket already reserved for this operation (workgroup
+// aggregation; Threshold was checked before reserving it).  It is always
+// tried: a Head ticket that no dequeuer visits could strand an item.
 template <bool ACQUIRE>
 __device__ __forceinline__ uint32_t ring_deq(const WRing& r, const gq_dev& q, uint32_t tid,
-                                             uint32_t& cf) {
+                                             uint32_t& cf, uint64_t first = NO_TICKET) {
   uint64_t last = NO_TICKET;
-  for (uint32_t a = 0;; a++) {
+  if (first != NO_TICKET) {
+    const uint32_t res = try_deq<ACQUIRE>(r, first, cf);
+    if (res != DEQ_RETRY) return res;
+    last = first;
+  }
+  for (uint32_t a = first != NO_TICKET ? 1u : 0u;; a++) {
     if (ld(r.g.thr) < 0) return BOT;
     if (a >= q.patience_deq) break;
     const uint64_t h = ticket(wave_faa(r.g.head, UNIT));
@@ -564,6 +582,53 @@ __device__ __forceinline__ int dequeue_impl(const gq_dev& q, uint64_t* item, uin
   *item = lfq::payload_get<FENCED>(q, idx);
   ring_enq<FENCED>(fq, q, tid, idx, cf);
   return GQ_OK;
+}
+
+// ---- workgroup-uniform form (see lfq::group_op) ----------------------------
+__device__ __forceinline__ uint64_t group_decode(uint64_t word) {
+  return word == GROUP_NONE ? NO_TICKET : ticket(word);
+}
+
+template <bool FENCED>
+__device__ __forceinline__ int group_op_impl(const gq_dev& q, int role, uint64_t& item,
+                                             uint32_t tid, uint32_t& cf, GroupLds& s,
+                                             uint32_t& par) {
+  int st = role == ROLE_ENQ ? GQ_FULL : role == ROLE_DEQ ? GQ_EMPTY : GQ_OK;
+  if (role != ROLE_NONE && tid >= q.max_threads) {
+    latch_error(q.err, (uint64_t)(-GQ_ERR_INVALID));
+    st = GQ_ERR_INVALID;
+    role = ROLE_NONE;
+  }
+  if (role != ROLE_NONE) help_check(q, tid);
+  const WRing fq = make_wring(q.fq, q);
+  const WRing aq = make_wring(q.aq, q);
+  const bool wf = role == ROLE_ENQ && ld(fq.g.thr) >= 0;
+  const bool wa = role == ROLE_DEQ && ld(aq.g.thr) >= 0;
+  uint64_t t = group_decode(group_ticket(s, par, fq.g.head, UNIT, wf, aq.g.head, UNIT, wa));
+  uint32_t idx = BOT;
+  if (wf) idx = ring_deq<false>(fq, q, tid, cf, t);
+  else if (wa) idx = ring_deq<FENCED>(aq, q, tid, cf, t);
+  if (idx != BOT && idx >= q.capacity) {
+    latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
+    idx = BOT;
+  }
+  if (idx != BOT) {
+    if (role == ROLE_ENQ) lfq::payload_put<FENCED>(q, idx, item);
+    else item = lfq::payload_get<FENCED>(q, idx);
+    st = GQ_OK;
+  }
+  const bool we = role == ROLE_ENQ && idx != BOT;
+  const bool wd = role == ROLE_DEQ && idx != BOT;
+  t = group_decode(group_ticket(s, par, aq.g.tail, UNIT, we, fq.g.tail, UNIT, wd));
+  if (we) ring_enq<FENCED>(aq, q, tid, idx, cf, t);
+  else if (wd) ring_enq<FENCED>(fq, q, tid, idx, cf, t);
+  return st;
+}
+
+__device__ __forceinline__ int group_op(const gq_dev& q, int role, uint64_t& item, uint32_t tid,
+                                        uint32_t& cf, GroupLds& s, uint32_t& par) {
+  return (q.flags & GQ_OPT_FENCED) ? group_op_impl<true>(q, role, item, tid, cf, s, par)
+                                   : group_op_impl<false>(q, role, item, tid, cf, s, par);
 }
 
 __device__ __forceinline__ int enqueue(const gq_dev& q, uint64_t item, uint32_t tid, uint32_t& cf) {

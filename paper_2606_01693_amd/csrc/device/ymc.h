@@ -151,8 +151,11 @@ __device__ __forceinline__ uint64_t help_enq(const Q& y, Handle* h, Cell* c, uin
 }
 
 // ---- enqueue -------------------------------------------------------------------
-__device__ __forceinline__ bool enq_fast(const Q& y, uint64_t v, uint64_t& id) {
-  const uint64_t i = wave_faa(y.T, 1);
+// `first`: a T ticket already reserved for this attempt (workgroup
+// aggregation), or GROUP_NONE.
+__device__ __forceinline__ bool enq_fast(const Q& y, uint64_t v, uint64_t& id,
+                                         uint64_t first = GROUP_NONE) {
+  const uint64_t i = first != GROUP_NONE ? first : wave_faa(y.T, 1);
   Cell* c = cell(y, i);
   if (!c) return true;  // pool exhausted: error latched, give up
   uint64_t e = BOT;
@@ -182,19 +185,20 @@ __device__ __forceinline__ void enq_slow(const Q& y, uint32_t tid, uint64_t v, u
   if (c) enq_commit(y, c, v, id);
 }
 
-__device__ __forceinline__ int enqueue(const gq_dev& q, uint64_t item, uint32_t tid, uint32_t& cf) {
-  const Q y = make_q(q);
-  if (tid >= y.k || (q.item_width == 8 && item >= RES_EMPTY - 1)) {
-    latch_error(q.err, (uint64_t)(-GQ_ERR_INVALID));
-    return GQ_ERR_INVALID;
-  }
+__device__ __forceinline__ bool enq_valid(const gq_dev& q, uint64_t item, uint32_t tid) {
+  return tid < q.max_threads && !(q.item_width == 8 && item >= RES_EMPTY - 1);
+}
+
+__device__ __forceinline__ int enqueue_impl(const Q& y, const gq_dev& q, uint64_t item,
+                                            uint32_t tid, uint32_t& cf, uint64_t first) {
   const uint64_t v = (q.item_width == 8 ? item : (item & 0xFFFFFFFFull)) + 1;
   uint64_t id = 0;
   // At least one fast attempt: the slow path starts from the cell that
   // attempt took (patience 0 means "one attempt, then the slow path").
   const uint32_t pat = y.patience_enq ? y.patience_enq : 1;
   for (uint32_t p = 0; p < pat; p++) {
-    if (enq_fast(y, v, id)) return ld(y.err) ? GQ_ERR_POOL_EXHAUSTED : GQ_OK;
+    if (enq_fast(y, v, id, p == 0 ? first : GROUP_NONE))
+      return ld(y.err) ? GQ_ERR_POOL_EXHAUSTED : GQ_OK;
     cf++;
   }
   faa(y.stats + S_SLOW, 1ull);
@@ -202,9 +206,21 @@ __device__ __forceinline__ int enqueue(const gq_dev& q, uint64_t item, uint32_t 
   return GQ_OK;
 }
 
+__device__ __forceinline__ int enqueue(const gq_dev& q, uint64_t item, uint32_t tid, uint32_t& cf) {
+  if (!enq_valid(q, item, tid)) {
+    latch_error(q.err, (uint64_t)(-GQ_ERR_INVALID));
+    return GQ_ERR_INVALID;
+  }
+  return enqueue_impl(make_q(q), q, item, tid, cf, GROUP_NONE);
+}
+
 // ---- dequeue -------------------------------------------------------------------
+// A relaxed look at the helpee's state comes first: with no request pending
+// (the common case) helping costs one load and no cache invalidation; a
+// request published after the look is helped on a later visit.
 __device__ void help_deq(const Q& y, Handle* h, uint32_t helpee) {
   Handle* r = &y.hd[helpee];
+  if (!(ld(&r->deq_state) & PENDING)) return;
   uint64_t s = ld_acq(&r->deq_state);
   const uint64_t id = ld_acq(&r->deq_id);
   if (!(s & PENDING) || (s & ID_MASK) < id) return;
@@ -244,8 +260,10 @@ __device__ void help_deq(const Q& y, Handle* h, uint32_t helpee) {
 }
 
 // deq_fast: returns a stored value, RES_EMPTY, or TOP (try again / go slow).
-__device__ __forceinline__ uint64_t deq_fast(const Q& y, Handle* h, uint64_t& id) {
-  const uint64_t i = wave_faa(y.H, 1);
+// `first`: an H ticket already reserved for this attempt, or GROUP_NONE.
+__device__ __forceinline__ uint64_t deq_fast(const Q& y, Handle* h, uint64_t& id,
+                                             uint64_t first = GROUP_NONE) {
+  const uint64_t i = first != GROUP_NONE ? first : wave_faa(y.H, 1);
   Cell* c = cell(y, i);
   if (!c) return RES_EMPTY;
   const uint64_t v = help_enq(y, h, c, i);
@@ -269,19 +287,15 @@ __device__ __forceinline__ uint64_t deq_slow(const Q& y, uint32_t tid, uint64_t 
   return v == TOP ? RES_EMPTY : v;
 }
 
-__device__ __forceinline__ int dequeue(const gq_dev& q, uint64_t* item, uint32_t tid, uint32_t& cf) {
-  const Q y = make_q(q);
-  if (tid >= y.k) {
-    latch_error(q.err, (uint64_t)(-GQ_ERR_INVALID));
-    return GQ_ERR_INVALID;
-  }
+__device__ __forceinline__ int dequeue_impl(const Q& y, uint64_t* item, uint32_t tid,
+                                            uint32_t& cf, uint64_t first) {
   Handle* me = &y.hd[tid];
   uint64_t v = TOP, id = 0;
   // At least one fast attempt: every cell a dequeuer takes from H must be
   // visited, and the slow path walks forward from the cell of the last one.
   const uint32_t pat = y.patience_deq ? y.patience_deq : 1;
   for (uint32_t p = 0; p < pat; p++) {
-    v = deq_fast(y, me, id);
+    v = deq_fast(y, me, id, p == 0 ? first : GROUP_NONE);
     if (v != TOP) break;
     cf++;
   }
@@ -297,6 +311,31 @@ __device__ __forceinline__ int dequeue(const gq_dev& q, uint64_t* item, uint32_t
   me->deq_peer = p + 1 >= y.k ? 0 : p + 1;
   *item = v - 1;
   return GQ_OK;
+}
+
+__device__ __forceinline__ int dequeue(const gq_dev& q, uint64_t* item, uint32_t tid, uint32_t& cf) {
+  if (tid >= q.max_threads) {
+    latch_error(q.err, (uint64_t)(-GQ_ERR_INVALID));
+    return GQ_ERR_INVALID;
+  }
+  return dequeue_impl(make_q(q), item, tid, cf, GROUP_NONE);
+}
+
+// ---- workgroup-uniform form (see lfq::group_op): one phase, the T ticket
+// of an enqueue or the H ticket of a dequeue comes from group_ticket.
+__device__ __forceinline__ int group_op(const gq_dev& q, int role, uint64_t& item, uint32_t tid,
+                                        uint32_t& cf, GroupLds& s, uint32_t& par) {
+  const Q y = make_q(q);
+  int st = GQ_OK;
+  if ((role == ROLE_ENQ && !enq_valid(q, item, tid)) || (role == ROLE_DEQ && tid >= y.k)) {
+    latch_error(q.err, (uint64_t)(-GQ_ERR_INVALID));
+    st = GQ_ERR_INVALID;
+    role = ROLE_NONE;
+  }
+  const uint64_t t = group_ticket(s, par, y.T, 1, role == ROLE_ENQ, y.H, 1, role == ROLE_DEQ);
+  if (role == ROLE_ENQ) st = enqueue_impl(y, q, item, tid, cf, t);
+  else if (role == ROLE_DEQ) st = dequeue_impl(y, &item, tid, cf, t);
+  return st;
 }
 
 }  // namespace ymc

@@ -39,6 +39,7 @@ static gq_status hip_fail(hipError_t e, const char* what, int line) {
 namespace {
 
 constexpr uint32_t kBlock = 256;
+constexpr uint32_t kDefaultGroupLanes = 1024;  // gq_options.ticket_group == 0
 constexpr uint64_t kCtrlBytes = 8192;
 constexpr uint64_t kLine = 256;  // counters live on separate 256-byte lines
 
@@ -93,6 +94,9 @@ gq_status plan(gq_kind kind, uint64_t n, uint32_t w, uint32_t k, const gq_option
   if (k == 0 || k > (1u << 24)) return GQ_ERR_INVALID;
   if (o && ((o->flags & ~(GQ_OPT_FENCED | GQ_OPT_WFQ_TUNING)) || o->slot_mode > GQ_SLOTS_LINEAR))
     return GQ_ERR_INVALID;
+  if (o && o->ticket_group &&
+      (!is_pow2(o->ticket_group) || o->ticket_group < 64 || o->ticket_group > 1024))
+    return GQ_ERR_INVALID;
   if (kind == GQ_WFQ) {
     if (k >= (1u << wfq::TID_BITS)) return GQ_ERR_INVALID;
     const bool tuned = o && (o->flags & GQ_OPT_WFQ_TUNING);
@@ -140,16 +144,18 @@ gq_status plan(gq_kind kind, uint64_t n, uint32_t w, uint32_t k, const gq_option
 // = Tail = 0, Threshold = -1.  Full free ring: tickets 0..n-1 already
 // enqueued in cycle 0 -- slots [0, n) hold <0, 1, i>, slots [n, 2n) empty --
 // Head = 0, Tail = n, Threshold = its reset value (3n - 1 when k <= n).
-__global__ void k_init_lfq(gq_dev q) {
+// The init functions take the calling lane's index g0 among `stride` lanes,
+// so that a whole grid (k_init_*) or one workgroup (a serving team setting
+// up a per-job queue in place) can run them.  Lane 0 writes the control words.
+__device__ void init_lfq_range(const gq_dev& q, uint64_t g0, uint64_t stride) {
   const uint64_t two_n = 2 * q.capacity;
   const lfq::Ring aq = lfq::make_ring(q.aq, q);
   const lfq::Ring fq = lfq::make_ring(q.fq, q);
-  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < two_n;
-       j += (uint64_t)gridDim.x * blockDim.x) {
+  for (uint64_t j = g0; j < two_n; j += stride) {
     st(aq.at(j), ~0ull);
     st(fq.at(j), j < q.capacity ? lfq::e_make(0, true, (uint32_t)j) : ~0ull);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (g0 == 0) {
     st(q.aq.head, 0ull);
     st(q.aq.tail, 0ull);
     st(q.aq.threshold, (int64_t)-1);
@@ -161,16 +167,19 @@ __global__ void k_init_lfq(gq_dev q) {
   }
 }
 
+__global__ void k_init_lfq(gq_dev q) {
+  init_lfq_range(q, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x,
+                 (uint64_t)gridDim.x * blockDim.x);
+}
+
 // G-WFQ rings: entries all ones in every field (Note = Cycle = -1 mod R,
 // Safe, Enq, BOT); the free ring holds <Note -1, cycle 0, Safe, Enq, i> in
 // slots [0, n).  Global words <counter, NULL>; records cleared, sequence
 // numbers start at 1, help counters staggered by lane.
-__global__ void k_init_wfq(gq_dev q) {
+__device__ void init_wfq_range(const gq_dev& q, uint64_t g0, uint64_t stride) {
   const uint64_t two_n = 2 * q.capacity;
   const lfq::Ring aq = lfq::make_ring(q.aq, q);
   const lfq::Ring fq = lfq::make_ring(q.fq, q);
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  const uint64_t g0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   for (uint64_t j = g0; j < two_n; j += stride) {
     st(aq.at(j), ~0ull);
     st(fq.at(j), j < q.capacity ? wfq::e_make(wfq::TAG_MASK, 0, true, true, (uint32_t)j) : ~0ull);
@@ -200,6 +209,11 @@ __global__ void k_init_wfq(gq_dev q) {
     st(q.err, 0ull);
     for (int s = 0; s < S_NUM; s++) st(q.stats + s, 0ull);
   }
+}
+
+__global__ void k_init_wfq(gq_dev q) {
+  init_wfq_range(q, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x,
+                 (uint64_t)gridDim.x * blockDim.x);
 }
 
 // G-WFQ-YMC: every cell empty {0, 0, 0}, T = H = 1 (cell id 0 doubles as
@@ -343,6 +357,39 @@ __global__ __launch_bounds__(256) void k_mix(gq_dev q, uint64_t seed, uint32_t o
   mix_lane<KIND, REC>(q, g, (uint32_t)g, seed, ops, counts, rec);
 }
 
+// The same workload with workgroup-aggregated first tickets: every lane of
+// the workgroup performs its op r together with the others (group_op), so
+// each ticket counter sees one FAA per workgroup per phase.  Same draws,
+// tokens and counts as k_mix.
+template <int KIND, bool REC>
+__global__ __launch_bounds__(1024) void k_mix_group(gq_dev q, uint64_t seed, uint32_t ops,
+                                                    uint64_t* counts, Rec rec) {
+  __shared__ GroupLds lds;
+  uint32_t par = 0;
+  const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  uint64_t seq = 0, ok_e = 0, ok_d = 0, full = 0, empty = 0;
+  uint32_t cf = 0;
+  for (uint32_t r = 0; r < ops; r++) {
+    const bool is_enq = (splitmix64(seed, (g << 32) | r) >> 63) == 0;
+    const uint64_t t0 = REC ? stamp() : 0;
+    uint64_t v = is_enq ? ((g << 32) | (seq + 1)) : 0;
+    const int s = gq_group_op_k<KIND>(q, is_enq ? ROLE_ENQ : ROLE_DEQ, v, (uint32_t)g, cf, lds,
+                                      par);
+    if (is_enq) {
+      if (s == GQ_OK) { seq++; ok_e++; } else full++;
+    } else {
+      if (s == GQ_OK) ok_d++; else { empty++; v = 0; }
+    }
+    if (REC) rec.put(g, r, is_enq ? 0 : 1, s, v, t0, end_stamp());
+  }
+  if (REC && rec.h.count) rec.h.count[g] = ops;
+  wave_add(counts + 0, ok_e);
+  wave_add(counts + 1, ok_d);
+  wave_add(counts + 2, full);
+  wave_add(counts + 3, empty);
+  wave_add(q.stats + S_CAS_FAIL, cf);
+}
+
 // Many independent queues in one launch: wavefront w works on queue
 // wave_q[w]; lane ids inside a queue start at q_lane0[queue].  The seed is
 // read from device memory so that a captured graph can advance it.
@@ -394,15 +441,17 @@ __global__ __launch_bounds__(256) void k_balanced(gq_dev q, uint32_t rounds, uin
 template <int KIND, bool REC>
 __global__ void k_prodcons(gq_dev q, uint64_t seed, const uint8_t* role, uint32_t quota,
                            uint64_t target, uint32_t log2_inv_p, uint32_t token_mode,
-                           uint32_t jitter, uint64_t max_rounds, uint64_t* taken,
-                           uint64_t* counts, Rec rec) {
+                           uint32_t jitter, uint64_t max_rounds, uint64_t limit_ticks,
+                           uint64_t* taken, uint64_t* counts, Rec rec) {
   const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   const bool producer = role[g] == 0;
   uint64_t seq = 0, ok_e = 0, ok_d = 0, full = 0, empty = 0;
+  uint64_t s1d = 0, s2d = 0, s1e = 0, s2e = 0;
   uint32_t cf = 0, r = 0;
+  const uint64_t t_start = limit_ticks ? stamp() : 0;
   for (uint64_t k = 0;; k++) {
     if (producer ? seq >= quota : ld(taken) >= target) break;
-    if (k >= max_rounds) {
+    if (k >= max_rounds || (limit_ticks && (k & 63) == 0 && stamp() - t_start > limit_ticks)) {
       latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
       break;
     }
@@ -414,12 +463,27 @@ __global__ void k_prodcons(gq_dev q, uint64_t seed, const uint8_t* role, uint32_
     if (producer) {
       const uint64_t v = token_mode == 0 ? ((g << 32) | (seq + 1)) : ((g << 20) | seq);
       const int s = gq_enqueue_k<KIND>(q, v, (uint32_t)g, cf);
-      if (s == GQ_OK) { seq++; ok_e++; } else full++;
+      if (s == GQ_OK) {
+        seq++;
+        ok_e++;
+        s1e += v;
+        s2e += v * v;
+      } else {
+        full++;
+      }
       if (REC) rec.put(g, r, 0, s, v, t0, end_stamp());
     } else {
       uint64_t v = 0;
       const int s = gq_dequeue_k<KIND>(q, &v, (uint32_t)g, cf);
-      if (s == GQ_OK) { ok_d++; faa(taken, 1ull); } else { empty++; v = 0; }
+      if (s == GQ_OK) {
+        ok_d++;
+        s1d += v;
+        s2d += v * v;
+        faa(taken, 1ull);
+      } else {
+        empty++;
+        v = 0;
+      }
       if (REC) rec.put(g, r, 1, s, v, t0, end_stamp());
     }
     r++;
@@ -429,6 +493,10 @@ __global__ void k_prodcons(gq_dev q, uint64_t seed, const uint8_t* role, uint32_
   wave_add(counts + 1, ok_d);
   wave_add(counts + 2, full);
   wave_add(counts + 3, empty);
+  wave_add(counts + 4, s1d);
+  wave_add(counts + 5, s2d);
+  wave_add(counts + 6, s1e);
+  wave_add(counts + 7, s2e);
   wave_add(q.stats + S_CAS_FAIL, cf);
 }
 
@@ -609,6 +677,61 @@ gq_status gq_required_bytes(gq_kind kind, uint64_t capacity, uint32_t item_width
   return GQ_OK;
 }
 
+// The device view of a queue laid out by plan() at `buf` (device memory).
+static gq_dev make_dev(gq_kind kind, uint64_t capacity, uint32_t item_width,
+                       uint32_t max_threads, const gq_options& o, char* buf,
+                       const Layout& L) {
+  gq_dev d;
+  memset(&d, 0, sizeof(d));
+  d.kind = kind;
+  d.item_width = item_width;
+  d.log2_cap = ilog2(capacity);
+  d.slot_mode = o.slot_mode;
+  d.max_threads = max_threads;
+  d.flags = o.flags;
+  d.capacity = capacity;
+  d.group_lanes = o.ticket_group ? o.ticket_group : kDefaultGroupLanes;
+  d.patience_enq = 16;
+  d.patience_deq = 64;
+  d.help_delay = 64;
+  if (o.flags & GQ_OPT_WFQ_TUNING) {
+    d.patience_enq = o.wfq_patience_enq;
+    d.patience_deq = o.wfq_patience_deq;
+    d.help_delay = o.wfq_help_delay;
+  }
+  d.data = buf + L.data;
+  d.aq.slots = (uint64_t*)(buf + L.slots_aq);
+  d.aq.head = (uint64_t*)(buf + OFF_AQ_HEAD);
+  d.aq.tail = (uint64_t*)(buf + OFF_AQ_TAIL);
+  d.aq.threshold = (int64_t*)(buf + OFF_AQ_THR);
+  d.fq.slots = (uint64_t*)(buf + L.slots_fq);
+  d.fq.head = (uint64_t*)(buf + OFF_FQ_HEAD);
+  d.fq.tail = (uint64_t*)(buf + OFF_FQ_TAIL);
+  d.fq.threshold = (int64_t*)(buf + OFF_FQ_THR);
+  if (kind == GQ_WFQ_YMC) {
+    d.ymc_cells = (uint64_t*)(buf + L.ymc_pool);
+    d.ymc_pool_cells = (o.ymc_pool_cells ? o.ymc_pool_cells : ymc_default_cells(capacity));
+    d.ymc_handles = buf + L.ymc_handles;
+    d.patience_enq = 10;  // the original algorithm's PATIENCE
+    d.patience_deq = 10;
+    if (o.flags & GQ_OPT_WFQ_TUNING) {
+      d.patience_enq = o.wfq_patience_enq;
+      d.patience_deq = o.wfq_patience_deq;
+    }
+  }
+  if (kind == GQ_WFQ) {
+    d.aq.records = buf + L.rec_aq;
+    d.fq.records = buf + L.rec_fq;
+    d.aq.owner = (uint64_t*)(buf + L.own_aq);
+    d.fq.owner = (uint64_t*)(buf + L.own_fq);
+    d.help_ctr = (uint32_t*)(buf + L.help);
+  }
+  d.err = (uint64_t*)(buf + OFF_ERR);
+  d.stats = (uint64_t*)(buf + OFF_STATS);
+  d.ymc_ctr = (uint64_t*)(buf + OFF_YMC_T);
+  return d;
+}
+
 gq_status gq_create(gq_kind kind, uint64_t capacity, uint32_t item_width, uint32_t max_threads,
                     const gq_options* opts, void* dev_buf, uint64_t buf_bytes, gq_queue** out) {
   if (!out) return GQ_ERR_INVALID;
@@ -644,57 +767,13 @@ gq_status gq_create(gq_kind kind, uint64_t capacity, uint32_t item_width, uint32
     q->bytes = L.total;
     q->owns = true;
   }
-  gq_dev& d = q->dev;
-  memset(&d, 0, sizeof(d));
-  d.kind = kind;
-  d.item_width = item_width;
-  d.log2_cap = ilog2(capacity);
-  d.slot_mode = q->opt.slot_mode;
-  d.max_threads = max_threads;
-  d.flags = q->opt.flags;
-  d.capacity = capacity;
-  d.patience_enq = 16;
-  d.patience_deq = 64;
-  d.help_delay = 64;
-  if (q->opt.flags & GQ_OPT_WFQ_TUNING) {
-    d.patience_enq = q->opt.wfq_patience_enq;
-    d.patience_deq = q->opt.wfq_patience_deq;
-    d.help_delay = q->opt.wfq_help_delay;
-  }
-  d.data = q->buf + L.data;
-  d.aq.slots = (uint64_t*)(q->buf + L.slots_aq);
-  d.aq.head = (uint64_t*)(q->buf + OFF_AQ_HEAD);
-  d.aq.tail = (uint64_t*)(q->buf + OFF_AQ_TAIL);
-  d.aq.threshold = (int64_t*)(q->buf + OFF_AQ_THR);
-  d.fq.slots = (uint64_t*)(q->buf + L.slots_fq);
-  d.fq.head = (uint64_t*)(q->buf + OFF_FQ_HEAD);
-  d.fq.tail = (uint64_t*)(q->buf + OFF_FQ_TAIL);
-  d.fq.threshold = (int64_t*)(q->buf + OFF_FQ_THR);
-  if (kind == GQ_WFQ_YMC) {
-    d.ymc_cells = (uint64_t*)(q->buf + L.ymc_pool);
-    d.ymc_pool_cells = (q->opt.ymc_pool_cells ? q->opt.ymc_pool_cells : ymc_default_cells(capacity));
-    d.ymc_handles = q->buf + L.ymc_handles;
-    d.patience_enq = 10;  // the original algorithm's PATIENCE
-    d.patience_deq = 10;
-    if (q->opt.flags & GQ_OPT_WFQ_TUNING) {
-      d.patience_enq = q->opt.wfq_patience_enq;
-      d.patience_deq = q->opt.wfq_patience_deq;
-    }
-  }
-  if (kind == GQ_WFQ) {
-    d.aq.records = q->buf + L.rec_aq;
-    d.fq.records = q->buf + L.rec_fq;
-    d.aq.owner = (uint64_t*)(q->buf + L.own_aq);
-    d.fq.owner = (uint64_t*)(q->buf + L.own_fq);
-    d.help_ctr = (uint32_t*)(q->buf + L.help);
-  }
-  d.err = (uint64_t*)(q->buf + OFF_ERR);
-  d.stats = (uint64_t*)(q->buf + OFF_STATS);
-  d.ymc_ctr = (uint64_t*)(q->buf + OFF_YMC_T);
+  q->dev = make_dev(kind, capacity, item_width, max_threads, q->opt, q->buf, L);
   st = launch_init(q, nullptr);
   if (st == GQ_OK) {
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) st = hip_fail(e, "hipDeviceSynchronize", __LINE__);
+    // waits for the init kernel only (not for a serving kernel on its own
+    // non-blocking stream)
+    hipError_t e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize", __LINE__);
   }
   if (st != GQ_OK) {
     if (q->owns) (void)hipFree(q->buf);
@@ -804,12 +883,27 @@ static Rec make_rec(const gq_history* h) {
     default: return GQ_ERR_INVALID;                  \
   }
 
+// Workgroup size of the group-ticket drivers: the queue's ticket group,
+// halved until it divides `lanes`; 64 (or less) means the per-wavefront form.
+static uint32_t group_block(const gq_queue* q, uint64_t lanes) {
+  uint32_t b = q->dev.group_lanes;
+  while (b > 64 && lanes % b) b >>= 1;
+  return b;
+}
+
 template <int KIND>
 static void launch_mix(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t ops, uint64_t* counts,
                        const gq_history* hist, hipStream_t s) {
+  const Rec rec = make_rec(hist);
+  const uint32_t gb = group_block(q, lanes);
+  if (gb > 64) {
+    const dim3 grid(lanes / gb), block(gb);
+    if (hist) LAUNCH((k_mix_group<KIND, true>), grid, block, 0, s, q->dev, seed, ops, counts, rec);
+    else LAUNCH((k_mix_group<KIND, false>), grid, block, 0, s, q->dev, seed, ops, counts, rec);
+    return;
+  }
   const uint32_t b = lanes % kBlock == 0 ? kBlock : 64;
   const dim3 grid(lanes / b), block(b);
-  const Rec rec = make_rec(hist);
   if (hist) LAUNCH((k_mix<KIND, true>), grid, block, 0, s, q->dev, seed, ops, counts, rec);
   else LAUNCH((k_mix<KIND, false>), grid, block, 0, s, q->dev, seed, ops, counts, rec);
 }
@@ -859,23 +953,23 @@ template <int KIND>
 static void launch_prodcons(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t block,
                             const uint8_t* role, uint32_t quota, uint64_t target,
                             uint32_t log2_inv_p, uint32_t token_mode, uint32_t jitter,
-                            uint64_t max_rounds, uint64_t* taken, uint64_t* counts,
-                            const gq_history* hist, hipStream_t s) {
+                            uint64_t max_rounds, uint64_t limit_ticks, uint64_t* taken,
+                            uint64_t* counts, const gq_history* hist, hipStream_t s) {
   const Rec rec = make_rec(hist);
   const dim3 grid(lanes / block), blk(block);
   if (hist)
     LAUNCH((k_prodcons<KIND, true>), grid, blk, 0, s, q->dev, seed, role, quota, target,
-           log2_inv_p, token_mode, jitter, max_rounds, taken, counts, rec);
+           log2_inv_p, token_mode, jitter, max_rounds, limit_ticks, taken, counts, rec);
   else
     LAUNCH((k_prodcons<KIND, false>), grid, blk, 0, s, q->dev, seed, role, quota, target,
-           log2_inv_p, token_mode, jitter, max_rounds, taken, counts, rec);
+           log2_inv_p, token_mode, jitter, max_rounds, limit_ticks, taken, counts, rec);
 }
 
 gq_status gq_run_prodcons(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t block,
                           const uint8_t* d_lane_role, uint32_t items_per_producer,
                           uint64_t target, uint32_t log2_inv_p, uint32_t token_mode,
-                          uint32_t jitter, uint64_t max_rounds, uint64_t* d_counts,
-                          const gq_history* hist, void* stream) {
+                          uint32_t jitter, uint64_t max_rounds, uint32_t time_limit_ms,
+                          uint64_t* d_counts, const gq_history* hist, void* stream) {
   if (!q || !d_counts || !d_lane_role || lanes == 0 || block == 0 || block > 1024 ||
       block % 64 || lanes % block || log2_inv_p > 63 || token_mode > 1 || lanes > q->k)
     return GQ_ERR_INVALID;
@@ -889,9 +983,10 @@ gq_status gq_run_prodcons(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t b
   // The shared "taken" counter sits in the queue's control block.
   uint64_t* taken = (uint64_t*)(q->buf + OFF_TAKEN);
   HIP_OK(hipMemsetAsync(taken, 0, sizeof(uint64_t), S(stream)));
+  const uint64_t limit_ticks = (uint64_t)time_limit_ms * 100000ull;  // 100 MHz clock
   KIND_SWITCH(q->kind, launch_prodcons<K>(q, seed, lanes, block, d_lane_role, items_per_producer,
                                           target, log2_inv_p, token_mode, jitter, max_rounds,
-                                          taken, d_counts, hist, S(stream)));
+                                          limit_ticks, taken, d_counts, hist, S(stream)));
   HIP_OK(hipGetLastError());
   return GQ_OK;
 }
@@ -1181,3 +1276,5 @@ gq_status gq_bfs(gq_queue* qa, gq_queue* qb, const uint32_t* d_offsets, const ui
   HIP_OK(hipGetLastError());
   return GQ_OK;
 }
+
+#include "gq_serve.inc"

@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_2606_01693_amd", "libgq.so")
 
 def declared_functions():
     names = set()
-    for h in ("gq.h", "gq_bench.h"):
+    for h in ("gq.h", "gq_bench.h", "gq_serve.h"):
         text = open(os.path.join(ROOT, "include", h)).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
         for m in re.finditer(r"\b(gq_[a-z_0-9]+)\s*\(", text):
@@ -97,3 +97,27 @@ def test_wfq_layout_includes_records():
     wfq = b.required_bytes("wfq", 1 << 12, 8, 4096)
     # two rings of 64-byte records per lane plus per-slot owner hints
     assert wfq - lfq >= 2 * 4096 * 64 + 2 * (2 << 12) * 8
+
+
+@pytest.mark.parametrize("tg,ok", [(0, True), (64, True), (128, True), (1024, True),
+                                   (32, False), (96, False), (2048, False)])
+def test_ticket_group_validation(tg, ok):
+    """The ticket group must be 0 (default) or a power of two in 64..1024."""
+    from paper_2606_01693_amd import _binding as b
+    if ok:
+        assert b.required_bytes("lfq", 1 << 10, 8, 1024, ticket_group=tg) > 0
+    else:
+        with pytest.raises(b.GQError) as e:
+            b.required_bytes("lfq", 1 << 10, 8, 1024, ticket_group=tg)
+        assert e.value.status == b.GQ_ERR_INVALID
+
+
+def test_device_view_struct_matches_header():
+    """The ctypes mirror of gq_dev / gq_options has the header's field order."""
+    from paper_2606_01693_amd import _binding as b
+    hdr = open(os.path.join(ROOT, "include", "gq.h")).read()
+    assert "uint32_t ticket_group;" in hdr and "uint32_t group_lanes;" in hdr
+    names = [f[0] for f in b._Options._fields_]
+    assert names[-1] == "ticket_group"
+    dev = [f[0] for f in b._DevView._fields_]
+    assert dev[dev.index("help_delay") + 1] == "group_lanes"

@@ -180,10 +180,13 @@ def test_c1_role_split(kind, run):
     T = torch()
     seed = workloads.run_seed(1, run)
     n, lanes, block = 1 << 10, 1024, 256
-    q = make_queue(kind, n, width=4, lanes=lanes)
+    # G-WFQ-YMC: every poll of an empty queue takes a cell; size its pool for
+    # the consumers' polling
+    q = make_queue(kind, n, width=4, lanes=lanes,
+                   **({"ymc_pool_cells": 1 << 24} if kind == "ymc" else {}))
     prod_waves = workloads.producer_waves(seed, 16, 8)
     role = np.repeat(np.where(prod_waves, 0, 1), 64).astype(np.uint8)
-    counts = T.zeros(4, dtype=T.int64, device="cuda")
+    counts = T.zeros(8, dtype=T.int64, device="cuda")
     h = gq.History(lanes, 1 << 14)
     q.run_prodcons(seed, lanes, block, T.tensor(role, device="cuda"), 64, 32768, 0, 1, counts, h,
                    max_rounds=1 << 22)
@@ -296,15 +299,23 @@ def run_mix_checked(kind, n, lanes, ops, seed, slot_mode="linear", do_prefill=Tr
     drain = drain_fifo(q, n if BOUNDED[kind] else expect + 1)
     assert len(drain) == expect
     rep = check_history(hist, drain, prefill=pre, capacity=cap_of(kind, n))
-    assert_clean(rep, hist, drain, pre, tag=f"mix_{kind}_{n}_{lanes}_{ops}_{slot_mode}")
+    assert_clean(rep, hist, drain, pre,
+                 tag=f"mix_{kind}_{n}_{lanes}_{ops}_{slot_mode}_tg{opts.get('ticket_group', 0)}")
     return c
+
+
+# ticket_group 64: every wavefront takes its own tickets (WaveFAA alone);
+# 0: the default workgroup aggregation (1024 lanes, or the largest power of
+# two dividing the lane count).
+TICKET_GROUPS = [64, 0]
 
 
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("n,lanes,ops", [(2, 512, 64), (4, 1536, 32), (64, 16384, 16),
                                          (1 << 10, 16384, 32), (1 << 16, 65536, 16)])
-def test_mix_history(kind, n, lanes, ops):
-    run_mix_checked(kind, n, lanes, ops, workloads.run_seed(2, n))
+@pytest.mark.parametrize("tg", TICKET_GROUPS)
+def test_mix_history(kind, n, lanes, ops, tg):
+    run_mix_checked(kind, n, lanes, ops, workloads.run_seed(2, n), ticket_group=tg)
 
 
 @pytest.mark.parametrize("kind", ["lfq", "wfq"])
@@ -324,10 +335,11 @@ def test_mix_history_fenced_handoff(kind, n):
 
 
 @pytest.mark.parametrize("kind", KINDS)
-def test_mix_full_size(kind):
+@pytest.mark.parametrize("tg", TICKET_GROUPS)
+def test_mix_full_size(kind, tg):
     """The benchmark's configuration: capacity 2^20, 2048 x 256 lanes, 2^26
     operations, prefill n/2; the full history is checked."""
-    run_mix_checked(kind, 1 << 20, 2048 * 256, 128, workloads.run_seed(2, 0))
+    run_mix_checked(kind, 1 << 20, 2048 * 256, 128, workloads.run_seed(2, 0), ticket_group=tg)
 
 
 # ---------------------------------------------------------------------------
@@ -339,10 +351,10 @@ def test_mix_full_size(kind):
     (4, 256, 16, 0, 1), (64, 1024, 16, 0, 1), (64, 1024, 16, 1, 1), (1 << 10, 4096, 16, 0, 4),
     (1 << 10, 4096, 16, 2, 64), (16, 2048, 16, 0, 1),
 ])
-def test_wfq_forced_slow_path_mix(n, lanes, ops, patience, delay):
-    import paper_2606_01693_amd as gq
+@pytest.mark.parametrize("tg", TICKET_GROUPS)
+def test_wfq_forced_slow_path_mix(n, lanes, ops, patience, delay, tg):
     run_mix_checked("wfq", n, lanes, ops, workloads.run_seed(3, n + patience),
-                    patience=patience, help_delay=delay)
+                    patience=patience, help_delay=delay, ticket_group=tg)
 
 
 @pytest.mark.parametrize("run", range(3))
@@ -354,7 +366,7 @@ def test_wfq_forced_slow_path_role_split(run):
     q = make_queue("wfq", n, width=4, lanes=lanes, patience=0, help_delay=1)
     prod_waves = workloads.producer_waves(seed, 16, 8)
     role = np.repeat(np.where(prod_waves, 0, 1), 64).astype(np.uint8)
-    counts = T.zeros(4, dtype=T.int64, device="cuda")
+    counts = T.zeros(8, dtype=T.int64, device="cuda")
     h = gq.History(lanes, 1 << 14)
     q.run_prodcons(seed, lanes, block, T.tensor(role, device="cuda"), 16, 8192, 0, 1, counts, h,
                    max_rounds=1 << 22)
@@ -419,8 +431,10 @@ def test_wfq_tiny_histories_slow_path(chunk):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("n,lanes,ops,patience", [(64, 1024, 16, 0), (1 << 10, 4096, 16, 1),
                                                    (16, 2048, 16, 0)])
-def test_ymc_forced_slow_path_mix(n, lanes, ops, patience):
-    run_mix_checked("ymc", n, lanes, ops, workloads.run_seed(4, n + patience), patience=patience)
+@pytest.mark.parametrize("tg", TICKET_GROUPS)
+def test_ymc_forced_slow_path_mix(n, lanes, ops, patience, tg):
+    run_mix_checked("ymc", n, lanes, ops, workloads.run_seed(4, n + patience), patience=patience,
+                    ticket_group=tg)
 
 
 @pytest.mark.parametrize("run", range(2))
@@ -429,10 +443,12 @@ def test_ymc_forced_slow_path_role_split(run):
     T = torch()
     seed = workloads.run_seed(1, 200 + run)
     n, lanes, block = 1 << 10, 1024, 256
-    q = make_queue("ymc", n, width=4, lanes=lanes, patience=0)
+    # consumers poll an often-empty queue and every poll takes a cell: size
+    # the pool for the polling, not for the 8192 items
+    q = make_queue("ymc", n, width=4, lanes=lanes, patience=0, ymc_pool_cells=1 << 24)
     prod_waves = workloads.producer_waves(seed, 16, 8)
     role = np.repeat(np.where(prod_waves, 0, 1), 64).astype(np.uint8)
-    counts = T.zeros(4, dtype=T.int64, device="cuda")
+    counts = T.zeros(8, dtype=T.int64, device="cuda")
     h = gq.History(lanes, 1 << 14)
     q.run_prodcons(seed, lanes, block, T.tensor(role, device="cuda"), 16, 8192, 0, 1, counts, h,
                    max_rounds=1 << 22)
