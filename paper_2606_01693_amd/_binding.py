@@ -512,10 +512,11 @@ class Server:
         res = (_ServeResult * max(1, n))()
         mi = self.ring_slots if max_inflight is None else max_inflight
         _check(lib().gq_serve_run(self._h, n, reqs, arr.ctypes.data, mi, res), "gq_serve_run")
-        out = {f[0]: np.array([getattr(res[i], f[0]) for i in range(n)])
-               for f in _ServeResult._fields_}
-        out["level_hash"] = out["level_hash"].astype(np.uint64)
-        return out
+        # explicit dtypes: 64-bit hashes above 2^63 must not pass through float
+        dt = {ctypes.c_int64: np.int64, ctypes.c_uint64: np.uint64, ctypes.c_uint32: np.uint32,
+              ctypes.c_int32: np.int32}
+        return {name: np.array([getattr(res[i], name) for i in range(n)], dtype=dt[ct])
+                for name, ct in _ServeResult._fields_}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -153,8 +153,8 @@ def test_serve_budget_admission():
         reqs = [(pool[i]["off"], pool[i]["cols"], pool[i]["root"]) for i in pick]
         res = srv.run(reqs, np.zeros(len(reqs), dtype=np.int64))
         check(pool, pick, res)
-        ev = sorted([(a, b) for a, b in zip(res["admit_ns"], res["job_bytes"])] +
-                    [(d, -b) for d, b in zip(res["done_ns"], res["job_bytes"])],
+        ev = sorted([(int(a), int(b)) for a, b in zip(res["admit_ns"], res["job_bytes"])] +
+                    [(int(d), -int(b)) for d, b in zip(res["done_ns"], res["job_bytes"])],
                     key=lambda x: (x[0], x[1]))
         level = 0
         for _, b in ev:
