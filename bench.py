@@ -35,6 +35,10 @@ ITEM_BYTES = 8
 # two slot RMWs (8 B each, counted read + write), two slot loads, two
 # threshold loads, one payload access (see the design notes).
 BYTES_PER_OP = 2 * 16 + 2 * 8 + 2 * 8 + ITEM_BYTES
+# G-WFQ-YMC has no index rings: one cell RMW (16 B) and about one more cell
+# word access (the claim on dequeue, the value check on enqueue) per
+# successful operation, on 32-byte cells.
+BYTES_PER_OP_KIND = {"lfq": BYTES_PER_OP, "wfq": BYTES_PER_OP, "ymc": 32}
 HBM_PEAK_GBS = 8000.0
 
 # Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of the timed kernel, from the
@@ -93,6 +97,10 @@ def measure_probes(gq, torch):
     gq.probe_cas(slots, nslots, 128, lanes, 2)
     ms = timed(lambda: gq.probe_cas(slots, nslots, 128, lanes, 16))
     res["r_slot_cas_per_s"] = lanes * 16 / (ms * 1e-3)
+    # linear slots: the consecutive tickets of a wavefront share lines
+    gq.probe_cas(slots, nslots, 8, lanes, 2)
+    ms = timed(lambda: gq.probe_cas(slots, nslots, 8, lanes, 16))
+    res["r_slot_cas_linear_per_s"] = lanes * 16 / (ms * 1e-3)
     del slots
     n = 1 << 28  # 2 GiB per buffer
     src = torch.ones(n, dtype=torch.int64, device="cuda")
@@ -495,7 +503,7 @@ def main():
     queues, counts = {}, {}
     for kind in kinds:
         # G-WFQ-YMC's pool must cover every ticket of the run (no reset
-        # between steps): 2^29 cells of 32 B.
+        # between steps): 2^29 cells of 24 B (12 GiB).
         q = gq.Queue(kind, CAP, item_width=ITEM_BYTES, max_threads=LANES,
                      slot_mode=args.slot_mode, fenced=args.fenced,
                      ymc_pool_cells=(1 << 29) if kind == "ymc" else 0,
@@ -557,7 +565,8 @@ def main():
     value = ok_total / wall / 1e6
     dom = max(kinds, key=lambda k: variants[k]["kernel_ms_avg"])
     dv = variants[dom]
-    achieved_gbs = dv["ok_ops_per_step"] * BYTES_PER_OP / (dv["kernel_ms_avg"] * 1e-3) / 1e9
+    bpo = BYTES_PER_OP_KIND[dom]
+    achieved_gbs = dv["ok_ops_per_step"] * bpo / (dv["kernel_ms_avg"] * 1e-3) / 1e9
     traffic = TRAFFIC_PROFILE.get(dom)
     out = {
         "metric": "Mops/s enq+deq at 50/50 mix, 2^20-slot queue",
@@ -593,21 +602,30 @@ def main():
             "traffic": (traffic["bytes_per_launch"] if traffic and
                         kernel_sources_hash() == traffic["sources_sha256_16"] else None),
             "kernel": f"k_mix<{NAMES[dom]}>",
-            "bytes_per_ok_op": BYTES_PER_OP,
+            "bytes_per_ok_op": bpo,
         },
     }
     if not args.no_probes:
         p = measure_probes(gq, torch)
         # Each of the four ticket counters serves one of every two operations
         # (enqueues: fq.Head, aq.Tail; dequeues: aq.Head, fq.Tail), and one
-        # WaveFAA covers the a lanes of a wave taking the same branch (a = 32
-        # at a 50/50 mix).  Each successful op performs 2 slot RMWs.
-        a = 32.0
-        bound_ops = min(2 * a * p["r_ctr_wave_faa_per_s"],
-                        p["r_slot_cas_per_s"] / 2.0,
-                        p["hbm_copy_gbs"] * 1e9 / BYTES_PER_OP)
-        out["atomic_roofline"] = dict(p, bound_mops=bound_ops / 1e6, kernel=NAMES[dom],
-                                      frac=dv["mops"] * 1e6 / bound_ops)
+        # ticket FAA covers the a lanes of a ticket group taking the same
+        # branch (a = group / 2 at a 50/50 mix: 32 for one wavefront, 512
+        # for the default 1024-lane group).  Each successful op performs 2
+        # slot RMWs at the layout's stride.
+        group = args.ticket_group or 1024
+        a = group / 2.0
+        r_slot = p["r_slot_cas_linear_per_s" if args.slot_mode == "linear" else "r_slot_cas_per_s"]
+        per_kernel = {}
+        for k in kinds:
+            b = min(2 * a * p["r_ctr_wave_faa_per_s"], r_slot / 2.0,
+                    p["hbm_copy_gbs"] * 1e9 / BYTES_PER_OP_KIND[k])
+            per_kernel[NAMES[k]] = {"bound_mops": b / 1e6,
+                                    "frac": variants[k]["mops"] * 1e6 / b}
+        bound_ops = per_kernel[NAMES[dom]]["bound_mops"] * 1e6
+        out["atomic_roofline"] = dict(p, ticket_group=group, lanes_per_faa=a,
+                                      bound_mops=bound_ops / 1e6, kernel=NAMES[dom],
+                                      frac=dv["mops"] * 1e6 / bound_ops, per_kernel=per_kernel)
     for q in queues.values():
         q.close()
     queues.clear()

@@ -117,7 +117,7 @@ typedef struct gq_dev {
     gq_ring_view fq;           /* ring of free indices                        */
     uint64_t *err;             /* latched device error (0 = none)             */
     uint64_t *stats;           /* device counters, see gq_stats               */
-    uint64_t *ymc_cells;       /* G-WFQ-YMC cell pool (4 words per cell)      */
+    uint64_t *ymc_cells;       /* G-WFQ-YMC pool: val[P], enq[P], deq[P]      */
     uint64_t ymc_pool_cells;
     uint64_t *ymc_ctr;         /* G-WFQ-YMC T at [0], H at [32]               */
     void *ymc_handles;         /* G-WFQ-YMC per-lane handles                  */

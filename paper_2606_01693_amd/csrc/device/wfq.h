@@ -145,8 +145,8 @@ __device__ __forceinline__ void catchup(const WRing& r, uint64_t target) {
 
 // ---- finalization of slow-path enqueues ------------------------------------
 // Set FIN on lane p's enqueue request if its committed ticket is h.
-__device__ __forceinline__ bool try_fin(const WRing& r, uint32_t p, uint64_t h) {
-  Rec* R = &r.rec[p];
+__device__ __forceinline__ bool try_fin(Rec* rec, uint32_t p, uint64_t h) {
+  Rec* R = &rec[p];
   const uint64_t q1 = ld_acq(&R->req);
   if ((q1 & 3) != 3) return false;  // not a pending enqueue
   const uint64_t tag = (q1 >> 2) & L_TAG_MASK;
@@ -162,14 +162,17 @@ __device__ __forceinline__ bool try_fin(const WRing& r, uint32_t p, uint64_t h) 
 // A dequeuer found an Enq = 0 entry for its ticket h: the slow enqueue that
 // installed it may not have set FIN yet.  Set it before consuming, so that no
 // helper of that request starts another round after the slot is reused.
-__device__ __noinline__ void finalize_enq(const WRing& r, uint64_t h, uint64_t j) {
-  const uint64_t o = ld(&r.owner[j]);
-  if ((o >> TID_BITS) == (h & CTR_MASK) && (o & TID_MASK) && (o & TID_MASK) <= r.k) {
-    if (try_fin(r, (uint32_t)(o & TID_MASK) - 1, h)) return;
+// It takes the ring's fields as scalars: a reference to the ring would make
+// the caller keep its ring descriptors in private memory on every operation.
+__device__ __noinline__ void finalize_enq(Rec* rec, const uint64_t* owner, uint32_t k,
+                                          uint64_t* stats, uint64_t h, uint64_t j) {
+  const uint64_t o = ld(&owner[j]);
+  if ((o >> TID_BITS) == (h & CTR_MASK) && (o & TID_MASK) && (o & TID_MASK) <= k) {
+    if (try_fin(rec, (uint32_t)(o & TID_MASK) - 1, h)) return;
   }
-  faa(r.stats + S_SCAN, 1ull);
-  for (uint32_t p = 0; p < r.k; p++)
-    if (try_fin(r, p, h)) return;
+  faa(stats + S_SCAN, 1ull);
+  for (uint32_t p = 0; p < k; p++)
+    if (try_fin(rec, p, h)) return;
 }
 
 // ---- fast path (the G-LFQ fast path on this entry layout) -------------------
@@ -202,7 +205,7 @@ __device__ __forceinline__ uint32_t try_deq(const WRing& r, uint64_t h, uint32_t
   uint64_t e = ld(p);
   while (true) {
     if (e_cyc(e) == c && !idx_free(e_idx(e))) {
-      if (!e_enq(e)) finalize_enq(r, h, j);
+      if (!e_enq(e)) finalize_enq(r.rec, r.owner, r.k, r.stats, h, j);
       const uint64_t x = (uint64_t)(e_idx(e) ^ BOTC);
       if (ACQUIRE) fxor_acq(p, x); else fxor(p, x);
       return e_idx(e);
@@ -533,7 +536,7 @@ __device__ __forceinline__ uint32_t ring_deq(const WRing& r, const gq_dev& q, ui
   uint64_t* p = r.g.at(j);
   const uint64_t e = ld_acq(p);
   if (e_cyc(e) == r.cycle_of(H) && !idx_free(e_idx(e))) {
-    if (!e_enq(e)) finalize_enq(r, H, j);
+    if (!e_enq(e)) finalize_enq(r.rec, r.owner, r.k, r.stats, H, j);
     const uint64_t x = (uint64_t)(e_idx(e) ^ BOTC);
     if (ACQUIRE) fxor_acq(p, x); else fxor(p, x);
     return e_idx(e);

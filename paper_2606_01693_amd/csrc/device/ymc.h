@@ -12,8 +12,11 @@
 //
 // GPU adaptation (Section III-A): the linked segments and their hazard-
 // pointer reclamation are replaced by one preallocated pool with direct
-// arithmetic lookup, cell(i) = pool + i; running past the pool latches
-// GQ_ERR_POOL_EXHAUSTED.  Request "pointers" in cells are lane ids + 1 (0 is
+// arithmetic lookup; running past the pool latches GQ_ERR_POOL_EXHAUSTED.
+// The pool is a structure of arrays -- val[P], enq[P], deq[P] -- so cell i's
+// words are val + i, enq + i and deq + i: the consecutive cells that one
+// ticket FAA hands to a wavefront (or workgroup) sit in consecutive words, and
+// their atomics coalesce into a few lines instead of one sector per lane.  Request "pointers" in cells are lane ids + 1 (0 is
 // the empty marker, all ones the taken marker); request states pack
 // <pending:1 | id:63> into one 64-bit word.  Tickets come from the wave-
 // aggregated fetch-and-add, which yields the same ticket order as per-lane
@@ -36,12 +39,13 @@ constexpr uint64_t ID_MASK = PENDING - 1;
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 constexpr uint64_t RES_EMPTY = TOP - 1;   // internal: "queue was empty"
 
+// Addresses of one cell's three words.
 struct Cell {
-  uint64_t val;
-  uint64_t enq;   // 0, lane + 1 of the enqueue request reserved here, or TOP
-  uint64_t deq;   // 0, lane + 1 of the dequeue request served here, or TOP
-  uint64_t pad;
+  uint64_t* val;
+  uint64_t* enq;  // 0, lane + 1 of the enqueue request reserved here, or TOP
+  uint64_t* deq;  // 0, lane + 1 of the dequeue request served here, or TOP
 };
+constexpr uint32_t CELL_WORDS = 3;  // pool bytes = 24 per cell
 
 struct Handle {          // one per lane, 64 bytes
   uint64_t enq_val;      // enqueue request: value (stored form)
@@ -55,7 +59,7 @@ struct Handle {          // one per lane, 64 bytes
 };
 
 struct Q {
-  Cell* pool;
+  uint64_t* pool;   // val[cells], then enq[cells], then deq[cells]
   uint64_t cells;
   uint64_t* T;
   uint64_t* H;
@@ -68,7 +72,7 @@ struct Q {
 
 __device__ __forceinline__ Q make_q(const gq_dev& q) {
   Q y;
-  y.pool = (Cell*)q.ymc_cells;
+  y.pool = q.ymc_cells;
   y.cells = q.ymc_pool_cells;
   y.T = q.ymc_ctr;
   y.H = q.ymc_ctr + 32;
@@ -81,14 +85,17 @@ __device__ __forceinline__ Q make_q(const gq_dev& q) {
   return y;
 }
 
-// Cell lookup into the preallocated pool; NULL (and a latched error) when the
+// Cell lookup into the preallocated pool; false (and a latched error) when the
 // pool is exhausted.
-__device__ __forceinline__ Cell* cell(const Q& y, uint64_t i) {
+__device__ __forceinline__ bool cell(const Q& y, uint64_t i, Cell& c) {
   if (i >= y.cells) {
     latch_error(y.err, (uint64_t)(-GQ_ERR_POOL_EXHAUSTED));
-    return nullptr;
+    return false;
   }
-  return y.pool + i;
+  c.val = y.pool + i;
+  c.enq = y.pool + y.cells + i;
+  c.deq = y.pool + 2 * y.cells + i;
+  return true;
 }
 
 __device__ __forceinline__ void advance_end(uint64_t* E, uint64_t v) {
@@ -102,9 +109,9 @@ __device__ __forceinline__ bool try_claim(uint64_t* state, uint64_t id, uint64_t
   return cas_acqrel(state, e, cell_id);
 }
 
-__device__ __forceinline__ void enq_commit(const Q& y, Cell* c, uint64_t v, uint64_t cid) {
+__device__ __forceinline__ void enq_commit(const Q& y, const Cell& c, uint64_t v, uint64_t cid) {
   advance_end(y.T, cid + 1);
-  st(&c->val, v);
+  st(c.val, v);
 }
 
 // help_enq: make cell i decided for dequeuers.  Returns the cell's value, TOP
@@ -112,11 +119,11 @@ __device__ __forceinline__ void enq_commit(const Q& y, Cell* c, uint64_t v, uint
 // The cell's own words carry the value, so the cell CASes of the fast paths
 // are relaxed; request records (value, then state) are published with
 // release and read with acquire.
-__device__ __forceinline__ uint64_t help_enq(const Q& y, Handle* h, Cell* c, uint64_t i) {
+__device__ __forceinline__ uint64_t help_enq(const Q& y, Handle* h, const Cell& c, uint64_t i) {
   uint64_t e = BOT;
-  if (!cas(&c->val, e, TOP) && e != TOP) return e;
-  // c->val is TOP: help a pending slow-path enqueue use this cell
-  if (ld_acq(&c->enq) == BOT) {
+  if (!cas(c.val, e, TOP) && e != TOP) return e;
+  // the cell holds TOP: help a pending slow-path enqueue use this cell
+  if (ld_acq(c.enq) == BOT) {
     uint32_t p = 0;
     uint64_t s = 0;
     for (uint32_t spin = 0;; spin++) {
@@ -128,26 +135,26 @@ __device__ __forceinline__ uint64_t help_enq(const Q& y, Handle* h, Cell* c, uin
       h->enq_peer = p + 1 >= y.k ? 0 : p + 1;
     }
     uint64_t ee = BOT;
-    if ((s & PENDING) && (s & ID_MASK) <= i && !cas_acqrel(&c->enq, ee, (uint64_t)p + 1)) {
+    if ((s & PENDING) && (s & ID_MASK) <= i && !cas_acqrel(c.enq, ee, (uint64_t)p + 1)) {
       h->enq_help_id = s & ID_MASK;  // could not reserve: retry this request next time
     } else {
       h->enq_peer = p + 1 >= y.k ? 0 : p + 1;
     }
     ee = BOT;
-    if (ld_acq(&c->enq) == BOT) cas_acqrel(&c->enq, ee, TOP);
+    if (ld_acq(c.enq) == BOT) cas_acqrel(c.enq, ee, TOP);
   }
-  const uint64_t ce = ld_acq(&c->enq);
+  const uint64_t ce = ld_acq(c.enq);
   if (ce == TOP) return ld(y.T) <= i ? RES_EMPTY : TOP;
   Handle* r = &y.hd[ce - 1];
   const uint64_t s = ld_acq(&r->enq_state);
   const uint64_t v = ld_acq(&r->enq_val);
   if ((s & ID_MASK) > i) {
     // the request started after this cell: it cannot use it
-    if (ld(&c->val) == TOP && ld(y.T) <= i) return RES_EMPTY;
-  } else if (try_claim(&r->enq_state, s & ID_MASK, i) || (s == i && ld(&c->val) == TOP)) {
+    if (ld(c.val) == TOP && ld(y.T) <= i) return RES_EMPTY;
+  } else if (try_claim(&r->enq_state, s & ID_MASK, i) || (s == i && ld(c.val) == TOP)) {
     enq_commit(y, c, v, i);
   }
-  return ld_acq(&c->val);
+  return ld_acq(c.val);
 }
 
 // ---- enqueue -------------------------------------------------------------------
@@ -156,10 +163,10 @@ __device__ __forceinline__ uint64_t help_enq(const Q& y, Handle* h, Cell* c, uin
 __device__ __forceinline__ bool enq_fast(const Q& y, uint64_t v, uint64_t& id,
                                          uint64_t first = GROUP_NONE) {
   const uint64_t i = first != GROUP_NONE ? first : wave_faa(y.T, 1);
-  Cell* c = cell(y, i);
-  if (!c) return true;  // pool exhausted: error latched, give up
+  Cell c;
+  if (!cell(y, i, c)) return true;  // pool exhausted: error latched, give up
   uint64_t e = BOT;
-  if (cas(&c->val, e, v)) return true;
+  if (cas(c.val, e, v)) return true;
   id = i;
   return false;
 }
@@ -171,18 +178,18 @@ __device__ __forceinline__ void enq_slow(const Q& y, uint32_t tid, uint64_t v, u
   for (uint32_t spin = 0;; spin++) {
     if (spin >= SPIN_LIMIT) { latch_error(y.err, (uint64_t)(-GQ_ERR_DEVICE)); return; }
     const uint64_t i = wave_faa(y.T, 1);
-    Cell* c = cell(y, i);
-    if (!c) return;
+    Cell c;
+    if (!cell(y, i, c)) return;
     uint64_t e = BOT;
-    if (cas_acqrel(&c->enq, e, (uint64_t)tid + 1) && ld(&c->val) == BOT) {
+    if (cas_acqrel(c.enq, e, (uint64_t)tid + 1) && ld(c.val) == BOT) {
       try_claim(&me->enq_state, cell_id, i);
       break;
     }
     if (!(ld_acq(&me->enq_state) & PENDING)) break;
   }
   const uint64_t id = ld_acq(&me->enq_state) & ID_MASK;
-  Cell* c = cell(y, id);
-  if (c) enq_commit(y, c, v, id);
+  Cell c;
+  if (cell(y, id, c)) enq_commit(y, c, v, id);
 }
 
 __device__ __forceinline__ bool enq_valid(const gq_dev& q, uint64_t item, uint32_t tid) {
@@ -230,10 +237,10 @@ __device__ void help_deq(const Q& y, Handle* h, uint32_t helpee) {
     // look for a candidate cell until one is found or another helper announces one
     for (uint32_t walk = 0; !cand && (s & ID_MASK) == prior; walk++) {
       if (walk >= SPIN_LIMIT) { latch_error(y.err, (uint64_t)(-GQ_ERR_DEVICE)); return; }
-      Cell* c = cell(y, ++i);
-      if (!c) return;
+      Cell c;
+      if (!cell(y, ++i, c)) return;
       const uint64_t v = help_enq(y, h, c, i);
-      if (v == RES_EMPTY || (v != TOP && ld_acq(&c->deq) == BOT)) cand = i;
+      if (v == RES_EMPTY || (v != TOP && ld_acq(c.deq) == BOT)) cand = i;
       else s = ld_acq(&r->deq_state);
     }
     if (cand) {
@@ -242,10 +249,10 @@ __device__ void help_deq(const Q& y, Handle* h, uint32_t helpee) {
       s = ld_acq(&r->deq_state);
     }
     if (!(s & PENDING) || ld_acq(&r->deq_id) != id) return;
-    Cell* c = cell(y, s & ID_MASK);
-    if (!c) return;
+    Cell c;
+    if (!cell(y, s & ID_MASK, c)) return;
     uint64_t d = BOT;
-    if (ld_acq(&c->val) == TOP || cas_acqrel(&c->deq, d, (uint64_t)helpee + 1) ||
+    if (ld_acq(c.val) == TOP || cas_acqrel(c.deq, d, (uint64_t)helpee + 1) ||
         d == (uint64_t)helpee + 1) {
       uint64_t e = s;
       cas_acqrel(&r->deq_state, e, s & ID_MASK);
@@ -264,12 +271,12 @@ __device__ void help_deq(const Q& y, Handle* h, uint32_t helpee) {
 __device__ __forceinline__ uint64_t deq_fast(const Q& y, Handle* h, uint64_t& id,
                                              uint64_t first = GROUP_NONE) {
   const uint64_t i = first != GROUP_NONE ? first : wave_faa(y.H, 1);
-  Cell* c = cell(y, i);
-  if (!c) return RES_EMPTY;
+  Cell c;
+  if (!cell(y, i, c)) return RES_EMPTY;
   const uint64_t v = help_enq(y, h, c, i);
   if (v == RES_EMPTY) return RES_EMPTY;
   uint64_t d = BOT;
-  if (v != TOP && cas(&c->deq, d, TOP)) return v;
+  if (v != TOP && cas(c.deq, d, TOP)) return v;
   id = i;
   return TOP;
 }
@@ -280,9 +287,9 @@ __device__ __forceinline__ uint64_t deq_slow(const Q& y, uint32_t tid, uint64_t 
   st_rel(&me->deq_state, PENDING | cid);
   help_deq(y, me, tid);
   const uint64_t i = ld_acq(&me->deq_state) & ID_MASK;
-  Cell* c = cell(y, i);
-  if (!c) return RES_EMPTY;
-  const uint64_t v = ld_acq(&c->val);
+  Cell c;
+  if (!cell(y, i, c)) return RES_EMPTY;
+  const uint64_t v = ld_acq(c.val);
   advance_end(y.H, i + 1);
   return v == TOP ? RES_EMPTY : v;
 }

@@ -131,7 +131,7 @@ gq_status plan(gq_kind kind, uint64_t n, uint32_t w, uint32_t k, const gq_option
     if (cells < 2 || cells > (1ull << 34)) return GQ_ERR_INVALID;
     if (k >= (1u << 31)) return GQ_ERR_INVALID;
     L->ymc_pool = off;
-    off = align_up(off + cells * sizeof(ymc::Cell), 4096);
+    off = align_up(off + cells * ymc::CELL_WORDS * 8, 4096);
     L->ymc_handles = off;
     off = align_up(off + (uint64_t)k * sizeof(ymc::Handle), 4096);
   }
@@ -216,17 +216,13 @@ __global__ void k_init_wfq(gq_dev q) {
                  (uint64_t)gridDim.x * blockDim.x);
 }
 
-// G-WFQ-YMC: every cell empty {0, 0, 0}, T = H = 1 (cell id 0 doubles as
+// G-WFQ-YMC: every cell word 0 (val, enq and deq empty), T = H = 1 (cell id 0 doubles as
 // "no id"), handles cleared with peers staggered by lane.
 __global__ void k_init_ymc(gq_dev q) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const uint64_t g0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  ymc::Cell* pool = (ymc::Cell*)q.ymc_cells;
-  for (uint64_t i = g0; i < q.ymc_pool_cells; i += stride) {
-    st(&pool[i].val, 0ull);
-    st(&pool[i].enq, 0ull);
-    st(&pool[i].deq, 0ull);
-  }
+  const uint64_t words = (uint64_t)ymc::CELL_WORDS * q.ymc_pool_cells;  // val, enq, deq arrays
+  for (uint64_t i = g0; i < words; i += stride) st(q.ymc_cells + i, 0ull);
   ymc::Handle* hd = (ymc::Handle*)q.ymc_handles;
   for (uint64_t t = g0; t < q.max_threads; t += stride) {
     st(&hd[t].enq_val, 0ull);
