@@ -358,17 +358,17 @@ __global__ __launch_bounds__(256) void k_mix(gq_dev q, uint64_t seed, uint32_t o
 // each ticket counter sees one FAA per workgroup per phase.  Same draws,
 // tokens and counts as k_mix.
 template <int KIND, bool REC>
-__global__ __launch_bounds__(1024) void k_mix_group(gq_dev q, uint64_t seed, uint32_t ops,
-                                                    uint64_t* counts, Rec rec) {
-  __shared__ GroupLds lds;
+__device__ __forceinline__ void mix_group_body(const gq_dev& q, uint64_t seed, uint32_t ops,
+                                               uint64_t* counts, const Rec& rec, GroupLds& lds) {
   uint32_t par = 0;
   const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  uint64_t seq = 0, ok_e = 0, ok_d = 0, full = 0, empty = 0;
+  // per-lane counts never exceed `ops` (< 2^32): 32-bit registers suffice
+  uint32_t seq = 0, ok_e = 0, ok_d = 0, full = 0, empty = 0;
   uint32_t cf = 0;
   for (uint32_t r = 0; r < ops; r++) {
     const bool is_enq = (splitmix64(seed, (g << 32) | r) >> 63) == 0;
     const uint64_t t0 = REC ? stamp() : 0;
-    uint64_t v = is_enq ? ((g << 32) | (seq + 1)) : 0;
+    uint64_t v = is_enq ? ((g << 32) | (uint64_t)(seq + 1)) : 0;
     const int s = gq_group_op_k<KIND>(q, is_enq ? ROLE_ENQ : ROLE_DEQ, v, (uint32_t)g, cf, lds,
                                       par);
     if (is_enq) {
@@ -384,6 +384,13 @@ __global__ __launch_bounds__(1024) void k_mix_group(gq_dev q, uint64_t seed, uin
   wave_add(counts + 2, full);
   wave_add(counts + 3, empty);
   wave_add(q.stats + S_CAS_FAIL, cf);
+}
+
+template <int KIND, bool REC>
+__global__ __launch_bounds__(1024) void k_mix_group(gq_dev q, uint64_t seed, uint32_t ops,
+                                                    uint64_t* counts, Rec rec) {
+  __shared__ GroupLds lds;
+  mix_group_body<KIND, REC>(q, seed, ops, counts, rec, lds);
 }
 
 // Many independent queues in one launch: wavefront w works on queue
