@@ -266,6 +266,13 @@ def test_tiny_histories_linearizable(kind, chunk):
         rows += [(99, 1, 1, 0, tmax + 2 * len(drain), tmax + 2 * len(drain) + 1)]
         ok, _ = oracle.check_linearizable(rows, capacity=n if BOUNDED[kind] else None,
                                           prefill=pre)
+        if not ok:
+            import os
+            os.makedirs("gpurun_out", exist_ok=True)
+            with open(f"gpurun_out/fail_tiny_{kind}_{chunk}_{trial}.txt", "w") as f:
+                f.write(f"prefill {pre}\n")
+                for r in sorted(rows, key=lambda x: x[4]):
+                    f.write(" ".join(str(x) for x in r) + "\n")
         assert ok, (trial, rows, pre)
         rep = check_history(hist, drain, prefill=pre, capacity=cap_of(kind, n))
         assert_clean(rep, hist, drain, pre, tag=f"tiny_{kind}_{chunk}_{trial}")
