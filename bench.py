@@ -426,6 +426,68 @@ def bench_serve(gq, torch, njobs=1000, pool_size=64, team_lanes=1024, budget=16 
     return out
 
 
+def bench_c2(gq, torch, kinds, seed, args):
+    """The throughput sweep's other points: (a) the mixed 50/50 workload with
+    2^26 attempts split over G = 1, 2, 4, ..., 2048 workgroups of 256 lanes;
+    (b) 32 fill/drain rounds through the host batch API (enqueue a batch of
+    n = 2^20 items, then dequeue a batch of n).  Kernel time by events."""
+    out = {"mix_by_workgroups": {}, "fill_drain": {}}
+    total = 1 << 26
+    for kind in kinds:
+        q = gq.Queue(kind, CAP, item_width=ITEM_BYTES, max_threads=LANES,
+                     ymc_pool_cells=(1 << 29) if kind == "ymc" else 0,
+                     ticket_group=args.ticket_group)
+        pre = torch.arange(1, CAP // 2 + 1, dtype=torch.int64, device="cuda") | (0xFFFFFFFF << 32)
+        q.enqueue_batch(pre)
+        counts = torch.zeros(4, dtype=torch.int64, device="cuda")
+        row = {}
+        g = 1
+        while g <= 2048:
+            lanes = g * 256
+            ops = total // lanes
+            counts.zero_()
+            e0, e1 = _events(torch)
+            e0.record()
+            q.run_mix(seed + 900 + g, lanes, ops, counts)
+            e1.record()
+            torch.cuda.synchronize()
+            c = counts.cpu().tolist()
+            ms = e0.elapsed_time(e1)
+            row[str(g)] = {"ms": ms, "mops": (c[0] + c[1]) / (ms * 1e-3) / 1e6}
+            g *= 2
+        assert q.check_error() == gq.GQ_OK
+        out["mix_by_workgroups"][NAMES[kind]] = row
+        log(f"[bench] c2 sweep {NAMES[kind]}: " +
+            ", ".join(f"G={k}: {v['mops']:.0f}" for k, v in row.items()))
+        q.close()
+        q = gq.Queue(kind, CAP, item_width=ITEM_BYTES, max_threads=LANES,
+                     ymc_pool_cells=(1 << 27) if kind == "ymc" else 0,
+                     ticket_group=args.ticket_group)
+        items = torch.arange(1, CAP + 1, dtype=torch.int64, device="cuda")
+        outb = torch.zeros(CAP, dtype=torch.int64, device="cuda")
+        nok = torch.zeros(1, dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch)
+        e0.record()
+        for _ in range(32):
+            q.enqueue_batch(items, num_ok=nok)
+            q.dequeue_batch(outb, num_ok=nok)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        ok = int(nok.item())
+        good = ok == 64 * CAP and q.check_error() == gq.GQ_OK and \
+            bool(torch.equal(outb.sort().values, items))
+        out["fill_drain"][NAMES[kind]] = {"ms": ms, "mops": ok / (ms * 1e-3) / 1e6,
+                                          "all_ok_and_last_round_conserved": good}
+        log(f"[bench] c2 fill/drain {NAMES[kind]}: {ms:.2f} ms, {ok / (ms * 1e-3) / 1e6:.0f} "
+            f"Mops/s, ok={good}")
+        q.close()
+        del pre, items, outb
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_c3(gq, torch, kinds=("lfq", "ymc"), items=1 << 23, cap=1 << 16, waves=1024):
     """Imbalanced producer/consumer runs: 1024 wavefronts of which the seed
     makes 128, 512 or 896 producers; a lane is active in a round with
@@ -493,6 +555,7 @@ def main():
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-c2", action="store_true")
     ap.add_argument("--ticket-group", type=int, default=0,
                     help="lanes per ticket FAA in the step (64 = one wavefront; 0 = 1024)")
     ap.add_argument("--no-ablation", action="store_true")
@@ -648,6 +711,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_ablation:
         out["ticket_ablation"] = bench_ticket_ablation(gq, torch, kinds, base_seed, args)
+    if not args.no_c2:
+        out["c2_sweep"] = bench_c2(gq, torch, kinds, base_seed, args)
     if not args.no_multi:
         out["batched_multi_queue"] = bench_multi(gq, torch)
         log(f"[bench] multi: {out['batched_multi_queue']}")

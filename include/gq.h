@@ -171,7 +171,8 @@ gq_status gq_reset(gq_queue *q, void *stream);
  * each tried once by its own lane, concurrently, with no order among them.
  * d_status (nullable): one byte per item, GQ_OK or GQ_FULL.
  * d_num_ok (nullable): a device uint64 to which the OK count is ADDED.
- * Batches issued on one stream take effect in stream order.                   */
+ * Batches issued on one stream take effect in stream order.  The first
+ * ticket of each operation is taken once per gq_options.ticket_group lanes.  */
 gq_status gq_enqueue_batch(gq_queue *q, const void *d_items, uint64_t m,
                            uint8_t *d_status, uint64_t *d_num_ok, void *stream);
 

@@ -291,6 +291,66 @@ __global__ void k_dequeue_batch(gq_dev q, void* out, uint64_t m, uint8_t* status
   if (nok) wave_add(nok, ok);
 }
 
+// Workgroup-uniform batches: every lane of a workgroup steps through the
+// items together (strides of the whole launch); lanes past the end take part
+// with ROLE_NONE so the group's ticket FAAs stay uniform.  The launch has at
+// most max_threads lanes, so lane ids are valid tids.
+template <int KIND>
+__global__ __launch_bounds__(1024) void k_enqueue_batch_group(gq_dev q, const void* items,
+                                                              uint64_t m, uint8_t* status,
+                                                              uint64_t* nok) {
+  __shared__ GroupLds lds;
+  uint32_t par = 0;
+  const uint64_t gtid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t ok = 0;
+  uint32_t cf = 0;
+  for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < m; base += stride) {
+    const uint64_t i = base + threadIdx.x;
+    const bool act = i < m;
+    uint64_t item = 0;
+    if (act) item = q.item_width == 8 ? ((const uint64_t*)items)[i]
+                                      : (uint64_t)((const uint32_t*)items)[i];
+    const int s = gq_group_op_k<KIND>(q, act ? ROLE_ENQ : ROLE_NONE, item, (uint32_t)gtid, cf,
+                                      lds, par);
+    if (act) {
+      if (status) status[i] = (uint8_t)s;
+      ok += s == GQ_OK;
+    }
+  }
+  wave_add(q.stats + S_OK_ENQ, ok);
+  wave_add(q.stats + S_CAS_FAIL, cf);
+  if (nok) wave_add(nok, ok);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(1024) void k_dequeue_batch_group(gq_dev q, void* out, uint64_t m,
+                                                              uint8_t* status, uint64_t* nok) {
+  __shared__ GroupLds lds;
+  uint32_t par = 0;
+  const uint64_t gtid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t ok = 0;
+  uint32_t cf = 0;
+  for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < m; base += stride) {
+    const uint64_t i = base + threadIdx.x;
+    const bool act = i < m;
+    uint64_t v = 0;
+    const int s = gq_group_op_k<KIND>(q, act ? ROLE_DEQ : ROLE_NONE, v, (uint32_t)gtid, cf, lds,
+                                      par);
+    if (act) {
+      if (s != GQ_OK) v = 0;
+      if (q.item_width == 8) ((uint64_t*)out)[i] = v;
+      else ((uint32_t*)out)[i] = (uint32_t)v;
+      if (status) status[i] = (uint8_t)s;
+      ok += s == GQ_OK;
+    }
+  }
+  wave_add(q.stats + S_OK_DEQ, ok);
+  wave_add(q.stats + S_CAS_FAIL, cf);
+  if (nok) wave_add(nok, ok);
+}
+
 // ---- history recording -----------------------------------------------------
 struct Rec {
   gq_history h;
@@ -636,9 +696,31 @@ static uint32_t batch_grid(const gq_queue* q, uint64_t m) {
   return grid_for(m, kBlock, cap);
 }
 
+// Workgroup-ticket batches: workgroups of the queue's ticket group (at most
+// max_threads lanes in all, capped like the per-wavefront form); 0 when the
+// group is a single wavefront or max_threads is too small for a group.
+static uint32_t batch_group_block(const gq_queue* q, uint64_t m, uint32_t* grid) {
+  uint32_t b = q->dev.group_lanes;
+  while (b > 64 && b > q->k) b >>= 1;
+  if (b <= 64) return 0;
+  uint64_t g = (m + b - 1) / b;
+  uint64_t cap = q->k / b;
+  if (cap > 8192ull * kBlock / b) cap = 8192ull * kBlock / b;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  *grid = (uint32_t)g;
+  return b;
+}
+
 template <int KIND>
 static void launch_enq(gq_queue* q, const void* items, uint64_t m, uint8_t* st, uint64_t* nok,
                        hipStream_t s) {
+  uint32_t ggrid = 0;
+  const uint32_t gb = batch_group_block(q, m, &ggrid);
+  if (gb) {
+    LAUNCH(k_enqueue_batch_group<KIND>, dim3(ggrid), dim3(gb), 0, s, q->dev, items, m, st, nok);
+    return;
+  }
   const uint32_t grid = batch_grid(q, m);
   LAUNCH(k_enqueue_batch<KIND>, dim3(grid), dim3(kBlock), 0, s, q->dev, items, m, st,
                      nok);
@@ -646,6 +728,12 @@ static void launch_enq(gq_queue* q, const void* items, uint64_t m, uint8_t* st, 
 template <int KIND>
 static void launch_deq(gq_queue* q, void* out, uint64_t m, uint8_t* st, uint64_t* nok,
                        hipStream_t s) {
+  uint32_t ggrid = 0;
+  const uint32_t gb = batch_group_block(q, m, &ggrid);
+  if (gb) {
+    LAUNCH(k_dequeue_batch_group<KIND>, dim3(ggrid), dim3(gb), 0, s, q->dev, out, m, st, nok);
+    return;
+  }
   const uint32_t grid = batch_grid(q, m);
   LAUNCH(k_dequeue_batch<KIND>, dim3(grid), dim3(kBlock), 0, s, q->dev, out, m, st,
                      nok);

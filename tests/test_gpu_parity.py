@@ -120,11 +120,12 @@ def test_single_wave_closed_form(kind, seed):
 
 
 @pytest.mark.parametrize("kind", KINDS)
-def test_batches_are_stream_ordered(kind):
+@pytest.mark.parametrize("tg", [64, 0])
+def test_batches_are_stream_ordered(kind, tg):
     import paper_2606_01693_amd as gq
     T = torch()
     n = 1 << 12
-    q = make_queue(kind, n)
+    q = make_queue(kind, n, ticket_group=tg)
     a = T.arange(1, 1001, dtype=T.int64, device="cuda")
     b = T.arange(5001, 6501, dtype=T.int64, device="cuda")
     nok = T.zeros(1, dtype=T.int64, device="cuda")
@@ -146,13 +147,14 @@ def test_batches_are_stream_ordered(kind):
 
 @pytest.mark.parametrize("kind", [k for k in KINDS if BOUNDED[k]])
 @pytest.mark.parametrize("n", [2, 64, 1 << 14])
-def test_batch_capacity_exact(kind, n):
+@pytest.mark.parametrize("tg", [64, 0])
+def test_batch_capacity_exact(kind, n, tg):
     """With only enqueues in flight, a linearizable bounded queue accepts
     exactly capacity - size of them; with only dequeues, it returns exactly
     size items."""
     import paper_2606_01693_amd as gq
     T = torch()
-    q = make_queue(kind, n, lanes=512)
+    q = make_queue(kind, n, lanes=512, ticket_group=tg)
     m = n + 100
     items = T.arange(1, m + 1, dtype=T.int64, device="cuda")
     st = T.zeros(m, dtype=T.uint8, device="cuda")
