@@ -488,6 +488,51 @@ def bench_c2(gq, torch, kinds, seed, args):
     return out
 
 
+def bench_timed(gq, torch, kinds, reps=5, warmup_us=1000, window_us=5000):
+    """The paper's micro-benchmark form: fixed-duration balanced and split
+    kernels (producer fractions 25/50/75 %), T = 2^9 .. 2^15 lanes in
+    workgroups of 256, per-wavefront tickets, capacity 2^20 prefilled to n/2;
+    Mops/s = successful operations completed in the window / window, median
+    of 5.  G-WFQ runs the balanced form only: in a split run one side can
+    outpace the other and poll an empty (or full) queue, where its slow path
+    starves (see the design notes)."""
+    out = {}
+    for kind in kinds:
+        q = gq.Queue(kind, CAP, item_width=ITEM_BYTES, max_threads=1 << 15,
+                     ymc_pool_cells=(1 << 28) if kind == "ymc" else 0)
+        pre = torch.arange(1, CAP // 2 + 1, dtype=torch.int64, device="cuda") | (0xFFFFFFFF << 32)
+        counts = torch.zeros(4, dtype=torch.int64, device="cuda")
+        ctl = torch.zeros(4, dtype=torch.int64, device="cuda")
+        modes = [("balanced", 50), ("split", 25), ("split", 50), ("split", 75)]
+        if kind == "wfq":
+            modes = [("balanced", 50)]
+        res = {}
+        for mode, pct in modes:
+            key = "balanced" if mode == "balanced" else f"split{pct}"
+            row = {}
+            for lg in range(9, 16):
+                vals = []
+                for _ in range(reps):
+                    q.reset()
+                    q.enqueue_batch(pre)
+                    counts.zero_()
+                    q.run_timed(mode, 1 << lg, counts, ctl, prod_pct=pct, warmup_us=warmup_us,
+                                window_us=window_us)
+                    c = counts.cpu().tolist()
+                    vals.append((c[0] + c[1]) / (window_us * 1e-6) / 1e6)
+                row[str(1 << lg)] = float(np.median(vals))
+            if q.check_error() != gq.GQ_OK:
+                row["error"] = gq.status_str(q.check_error())
+            res[key] = row
+            log(f"[bench] timed {NAMES[kind]} {key}: " +
+                ", ".join(f"{k}: {v:.0f}" for k, v in row.items() if k != "error"))
+        out[NAMES[kind]] = res
+        q.close()
+        del pre
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_c3(gq, torch, kinds=("lfq", "ymc"), items=1 << 23, cap=1 << 16, waves=1024):
     """Imbalanced producer/consumer runs: 1024 wavefronts of which the seed
     makes 128, 512 or 896 producers; a lane is active in a round with
@@ -556,6 +601,7 @@ def main():
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-c2", action="store_true")
+    ap.add_argument("--no-timed", action="store_true")
     ap.add_argument("--ticket-group", type=int, default=0,
                     help="lanes per ticket FAA in the step (64 = one wavefront; 0 = 1024)")
     ap.add_argument("--no-ablation", action="store_true")
@@ -713,6 +759,8 @@ def main():
         out["ticket_ablation"] = bench_ticket_ablation(gq, torch, kinds, base_seed, args)
     if not args.no_c2:
         out["c2_sweep"] = bench_c2(gq, torch, kinds, base_seed, args)
+    if not args.no_timed:
+        out["fixed_duration"] = bench_timed(gq, torch, kinds)
     if not args.no_multi:
         out["batched_multi_queue"] = bench_multi(gq, torch)
         log(f"[bench] multi: {out['batched_multi_queue']}")

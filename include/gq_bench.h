@@ -111,6 +111,21 @@ gq_status gq_run_prodcons(gq_queue *q, uint64_t seed, uint32_t lanes, uint32_t b
                           uint32_t jitter, uint64_t max_rounds, uint32_t time_limit_ms,
                           uint64_t *d_counts, const gq_history *hist, void *stream);
 
+/* Fixed-duration run (Section V-A's balanced and split kernels): `lanes`
+ * lanes (a multiple of 256, all co-resident, at most max_threads) in
+ * workgroups of 256 work until warmup_us + window_us microseconds have passed
+ * on the GPU's constant clock since the first lane started; a successful
+ * operation counts when it completes inside the window.  mode 0 (balanced):
+ * every lane alternates enqueue and dequeue; mode 1 (split): the first
+ * prod_pct percent of the wavefronts only enqueue, the rest only dequeue.
+ * Each operation is tried once; tokens as in gq_run_mix.  d_counts[4] +=
+ * {enqueues OK in the window, dequeues OK in the window, FULL, EMPTY} (the
+ * last two over the whole run).  d_ctl: caller-owned device memory of at
+ * least 8 bytes (the shared start time), cleared by the call.               */
+gq_status gq_run_timed(gq_queue *q, uint32_t mode, uint32_t lanes, uint32_t prod_pct,
+                       uint32_t warmup_us, uint32_t window_us, uint64_t *d_counts,
+                       uint64_t *d_ctl, void *stream);
+
 /* Scripted run for small linearizability tests: lane g (< lanes <= 1024)
  * executes n_ops[g] operations from ops[g * max_ops ...] (0 enqueue,
  * 1 dequeue) with arguments args[...], pausing pause[g * max_ops + r] sleep

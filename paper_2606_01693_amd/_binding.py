@@ -32,6 +32,7 @@ EXPORTS = (
     "gq_resident_blocks", "gq_device_info", "gq_multi_create", "gq_multi_run_mix",
     "gq_multi_capture", "gq_multi_replay", "gq_multi_destroy", "gq_bfs",
     "gq_serve_create", "gq_serve_run", "gq_serve_job_bytes", "gq_serve_destroy",
+    "gq_run_timed",
 )
 
 
@@ -134,6 +135,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gq_multi_destroy": [P],
         "gq_bfs": [P, P, P, P, U32, U32, P, U32, U32, P, P],
         "gq_serve_create": [U32, U32, I32, U64, U32, U32, P],
+        "gq_run_timed": [P, U32, U32, U32, U32, U32, P, P, P],
         "gq_serve_run": [P, U32, P, P, U32, P],
         "gq_serve_job_bytes": [P, U32, U64, P],
         "gq_serve_destroy": [P],
@@ -351,6 +353,16 @@ class Queue:
                                      max_rounds, time_limit_ms, _ptr(counts),
                                      ctypes.byref(hc) if hc is not None else None,
                                      _stream(stream)), "gq_run_prodcons")
+
+    def run_timed(self, mode: str, lanes: int, counts, ctl, prod_pct: int = 50,
+                  warmup_us: int = 1000, window_us: int = 5000, stream=None):
+        """Fixed-duration run; mode 'balanced' or 'split'.  counts: 4 int64
+        words (added to); ctl: at least one int64 word of scratch."""
+        _need_words(counts, 4, "run_timed")
+        _need_words(ctl, 1, "run_timed ctl")
+        _check(lib().gq_run_timed(self._h, {"balanced": 0, "split": 1}[mode], lanes, prod_pct,
+                                  warmup_us, window_us, _ptr(counts), _ptr(ctl),
+                                  _stream(stream)), "gq_run_timed")
 
     def run_script(self, lanes: int, spread: bool, ops, args, pauses, n_ops, max_ops: int,
                    hist: History, stream=None):

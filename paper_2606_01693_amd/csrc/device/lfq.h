@@ -94,13 +94,15 @@ __device__ __forceinline__ Ring make_ring(const gq_ring_view& v, const gq_dev& q
   return r;
 }
 
-// Move Tail forward to at least h (sCQ catch-up, Algorithm 1 "catch up Tail").
-__device__ __forceinline__ void catchup(const Ring& r, uint64_t t, uint64_t h) {
-  while (!cas(r.tail, t, h)) {
-    h = ld(r.head);
-    t = ld(r.tail);
-    if (t >= h) break;
-  }
+// Move Tail forward to at least `target` (Algorithm 1 "catch up Tail").  The
+// CAS only ever raises Tail: it is attempted while the Tail it last read is
+// below the target, and a failed CAS returns the newer Tail.  (A CAS from a
+// freshly read Tail to a target below it would move Tail backward and hand a
+// used ticket to a later enqueuer.)
+__device__ __forceinline__ void catchup(const Ring& r, uint64_t target) {
+  uint64_t t = ld(r.tail);
+  for (uint32_t spin = 0; t < target && spin < SPIN_LIMIT; spin++)
+    if (cas(r.tail, t, target)) break;
 }
 
 // Inner enqueue of index `idx` (Algorithm 1, TryEnq, retried until success).
@@ -145,6 +147,26 @@ __device__ __forceinline__ bool ring_enq(const Ring& r, uint32_t idx, uint32_t& 
   return true;
 }
 
+// Entries a dequeuer could find right now: Tail - Head, read in that order
+// (Head first, and only after its value has returned, Tail), or 0 when Tail
+// <= Head.  Both counters sit in the bits above `shift` of their words.
+// Head and Tail only grow.  With Tail <= Head, every installed entry's
+// ticket is below Head, so a dequeuer already holds it and will consume it:
+// those dequeuers can be linearized just before the Tail read, in ticket
+// order, and the queue is empty there -- an EMPTY answer that takes (and
+// burns) no ticket.  When fewer entries than polling lanes are available,
+// only that many lanes of a wavefront take tickets; the others look again
+// instead of taking tickets past Tail, each of which would mark a slot and
+// make Tail catch up.
+__device__ __forceinline__ uint64_t poll_avail(uint64_t* head, uint64_t* tail, uint32_t shift) {
+  const uint64_t hh = read_first_lane(ld(head));
+  keep(hh);
+  wait_mem();
+  const uint64_t tt = read_first_lane(ld(tail));
+  const uint64_t hc = hh >> shift, tc = tt >> shift;
+  return tc > hc ? tc - hc : 0;
+}
+
 // Inner dequeue (Algorithm 1, TryDeq, retried until an index or EMPTY).
 // Returns the index, or BOT for EMPTY.  ACQUIRE makes Consume an agent-scope
 // acquire (fenced hand-off).  Consume is an atomic XOR that turns
@@ -168,7 +190,20 @@ __device__ __forceinline__ uint32_t ring_deq(const Ring& r, uint32_t& cas_fail, 
       h = first;
       first = GROUP_NONE;
     } else {
-      if (ld(r.thr) < 0) return BOT;
+      const int64_t th = ld(r.thr);
+      if (th < 0) return BOT;
+      // Threshold below its reset value: a dequeue failed since the last
+      // install, so the queue may be nearly empty -- look before taking a
+      // ticket.  (On a queue that keeps items, the look would only add two
+      // loads on the hottest lines.)
+      if (th < r.thr_reset) {
+        const uint64_t avail = poll_avail(r.head, r.tail, 0);
+        if (avail == 0) return BOT;
+        if (lane_rank(active_mask()) >= avail) {  // bounded grab: look again
+          pause(1);
+          continue;
+        }
+      }
       h = wave_faa(r.head, 1);
     }
     const uint32_t c = r.cycle_of(h);
@@ -203,7 +238,7 @@ __device__ __forceinline__ uint32_t ring_deq(const Ring& r, uint32_t& cas_fail, 
       const uint64_t target = wave_max(h + 1);
       const uint64_t mask = active_mask();
       if (lane_rank(mask) == 0) {
-        catchup(r, ld(r.tail), target);
+        catchup(r, target);
         faa(r.thr, -(int64_t)__popcll(mask));
       }
       return BOT;

@@ -513,8 +513,19 @@ __device__ __forceinline__ uint32_t ring_deq(const WRing& r, const gq_dev& q, ui
     last = first;
   }
   for (uint32_t a = first != NO_TICKET ? 1u : 0u;; a++) {
-    if (ld(r.g.thr) < 0) return BOT;
+    const int64_t th = ld(r.g.thr);
+    if (th < 0) return BOT;
     if (a >= q.patience_deq) break;
+    // empty pre-check and bounded grab on the counters while Threshold shows
+    // recent failures (see lfq::ring_deq and lfq::poll_avail)
+    if (th < r.g.thr_reset) {
+      const uint64_t avail = lfq::poll_avail(r.g.head, r.g.tail, TID_BITS);
+      if (avail == 0) return BOT;
+      if (lane_rank(active_mask()) >= avail) {  // looking again uses up an attempt
+        pause(1);
+        continue;
+      }
+    }
     const uint64_t h = ticket(wave_faa(r.g.head, UNIT));
     const uint32_t res = try_deq<ACQUIRE>(r, h, cf);
     if (res != DEQ_RETRY) return res;

@@ -563,6 +563,51 @@ __global__ void k_prodcons(gq_dev q, uint64_t seed, const uint8_t* role, uint32_
   wave_add(q.stats + S_CAS_FAIL, cf);
 }
 
+// ---- fixed-duration runs -----------------------------------------------------
+// Every lane reads the shared start time (the first lane to arrive sets it),
+// then works until start + warmup + window.  The clock is the scalar 100 MHz
+// counter, so all lanes of a wavefront leave the loop together.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_timed(gq_dev q, uint32_t mode, uint32_t prod_waves,
+                                               uint64_t warm_ticks, uint64_t win_ticks,
+                                               uint64_t* counts, uint64_t* ctl) {
+  const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  uint64_t start = ld(ctl);
+  if (start == 0) {
+    uint64_t z = 0;
+    const uint64_t now = stamp();
+    start = cas(ctl, z, now) ? now : z;
+  }
+  const uint64_t w0 = start + warm_ticks, w1 = w0 + win_ticks;
+  const bool producer = (g >> 6) < prod_waves;
+  uint32_t seq = 0, ok_e = 0, ok_d = 0, full = 0, empty = 0, cf = 0;
+  for (uint32_t r = 0;; r++) {
+    const bool enq = mode == 0 ? (r & 1) == 0 : producer;
+    int st;
+    if (enq) {
+      st = gq_enqueue_k<KIND>(q, (g << 32) | (uint64_t)(seq + 1), (uint32_t)g, cf);
+      if (st == GQ_OK) seq++;
+    } else {
+      uint64_t v = 0;
+      st = gq_dequeue_k<KIND>(q, &v, (uint32_t)g, cf);
+    }
+    const uint64_t t = stamp();
+    if (st == GQ_OK) {
+      if (t >= w0 && t < w1) {
+        if (enq) ok_e++; else ok_d++;
+      }
+    } else {
+      if (enq) full++; else empty++;
+    }
+    if (t >= w1) break;
+  }
+  wave_add(counts + 0, ok_e);
+  wave_add(counts + 1, ok_d);
+  wave_add(counts + 2, full);
+  wave_add(counts + 3, empty);
+  wave_add(q.stats + S_CAS_FAIL, cf);
+}
+
 // ---- scripted small runs ---------------------------------------------------
 template <int KIND>
 __global__ void k_script(gq_dev q, uint32_t lanes, uint32_t spread, const uint8_t* ops,
@@ -1078,6 +1123,28 @@ gq_status gq_run_prodcons(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t b
   KIND_SWITCH(q->kind, launch_prodcons<K>(q, seed, lanes, block, d_lane_role, items_per_producer,
                                           target, log2_inv_p, token_mode, jitter, max_rounds,
                                           limit_ticks, taken, d_counts, hist, S(stream)));
+  HIP_OK(hipGetLastError());
+  return GQ_OK;
+}
+
+gq_status gq_run_timed(gq_queue* q, uint32_t mode, uint32_t lanes, uint32_t prod_pct,
+                       uint32_t warmup_us, uint32_t window_us, uint64_t* d_counts,
+                       uint64_t* d_ctl, void* stream) {
+  if (!q || !d_counts || !d_ctl || mode > 1 || lanes == 0 || lanes % kBlock || lanes > q->k ||
+      prod_pct > 100 || window_us == 0)
+    return GQ_ERR_INVALID;
+  const void* fn = nullptr;
+  KIND_SWITCH(q->kind, fn = (const void*)k_timed<K>);
+  uint32_t resident = 0;
+  gq_status st = resident_blocks_of(fn, kBlock, &resident);
+  if (st != GQ_OK) return st;
+  if (lanes / kBlock > resident) return GQ_ERR_RESIDENCY;
+  const uint32_t waves = lanes / 64;
+  const uint32_t prod_waves = mode == 0 ? waves : (uint32_t)((uint64_t)waves * prod_pct / 100);
+  HIP_OK(hipMemsetAsync(d_ctl, 0, sizeof(uint64_t), S(stream)));
+  const uint64_t warm = (uint64_t)warmup_us * 100, win = (uint64_t)window_us * 100;
+  KIND_SWITCH(q->kind, LAUNCH(k_timed<K>, dim3(lanes / kBlock), dim3(kBlock), 0, S(stream),
+                              q->dev, mode, prod_waves, warm, win, d_counts, d_ctl));
   HIP_OK(hipGetLastError());
   return GQ_OK;
 }
