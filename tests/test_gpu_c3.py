@@ -81,10 +81,6 @@ FULL_SIZE_KINDS = [pytest.param(k, marks=pytest.mark.skip(
 @pytest.mark.parametrize("prod_waves", [128, 512, 896])
 @pytest.mark.parametrize("log2_inv_p", [0, 1, 6])
 def test_c3_full_size_conservation(kind, prod_waves, log2_inv_p):
-    if kind == "lfq" and log2_inv_p == 6 and prod_waves in (128, 896):
-        pytest.skip("p = 1/64 with 7:1 pollers: measured 3.1-3.9 M of 8.4 M items in 60 s; each "
-                    "item re-arms Threshold and ~900 polling wavefronts take a ticket each, "
-                    "while WaveFAA has about one lane per wavefront to aggregate")
     if kind == "ymc" and prod_waves == 128:
         pytest.skip("G-WFQ-YMC takes a cell per empty poll: 57,344 polling consumers exhaust "
                     "even 2^30 cells (its memory is not bounded, Section III-A)")
