@@ -51,11 +51,11 @@ KERNEL_SOURCES = ("paper_2606_01693_amd/csrc/device/common.h",
                   "paper_2606_01693_amd/csrc/gq_lib.hip")
 _PROFILE = "profiles/k_mix_group_mixed5050_cap2p20_ops2p26.md"
 TRAFFIC_PROFILE = {  # kind -> scaled FETCH_SIZE + WRITE_SIZE bytes per launch of the step kernel
-    "lfq": {"sources_sha256_16": "3e30400af85fdf6a", "bytes_per_launch": 4.026e9,
+    "lfq": {"sources_sha256_16": "5acb8e63d97b1247", "bytes_per_launch": 4.007e9,
             "profile": _PROFILE},
-    "wfq": {"sources_sha256_16": "3e30400af85fdf6a", "bytes_per_launch": 4.214e9,
+    "wfq": {"sources_sha256_16": "5acb8e63d97b1247", "bytes_per_launch": 4.205e9,
             "profile": _PROFILE},
-    "ymc": {"sources_sha256_16": "3e30400af85fdf6a", "bytes_per_launch": 3.482e9,
+    "ymc": {"sources_sha256_16": "5acb8e63d97b1247", "bytes_per_launch": 3.482e9,
             "profile": _PROFILE},
 }
 NAMES = {"lfq": "G-LFQ", "wfq": "G-WFQ", "ymc": "G-WFQ-YMC"}
