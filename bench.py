@@ -39,6 +39,11 @@ BYTES_PER_OP = 2 * 16 + 2 * 8 + 2 * 8 + ITEM_BYTES
 # word access (the claim on dequeue, the value check on enqueue) per
 # successful operation, on 32-byte cells.
 BYTES_PER_OP_KIND = {"lfq": BYTES_PER_OP, "wfq": BYTES_PER_OP, "ymc": 32}
+# Atomic read-modify-writes per successful operation (the coalesced RMW rate is
+# the bound once tickets are aggregated): the ring queues install (CAS),
+# consume (XOR) and hand the payload over (exchange); YMC CASes the cell value
+# on an enqueue, and on a dequeue CASes the value and claims the cell.
+RMW_PER_OP_KIND = {"lfq": 3.0, "wfq": 3.0, "ymc": 1.5}
 HBM_PEAK_GBS = 8000.0
 
 # Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of the timed kernel, from the
@@ -313,6 +318,12 @@ def bench_multi(gq, torch, kind="lfq", nq=256, ops=16, reps=5):
     m.close()
     for q in qs:
         q.close()
+    # the autotuner's lane allotment for the same queues and work per queue
+    from paper_2606_01693_amd import autotune
+    t = autotune.tune_multi(kind, caps, waves_per_256_slots=(0.5, 1, 2, 4), ops_factor=4, reps=3)
+    res["autotuned"] = {"waves_per_256_slots": t.best["waves_per_256_slots"],
+                        "ms_per_step": t.best_ms, "mops": t.best_mops,
+                        "table": [{k: v for k, v in row.items()} for row in t.table]}
     return res
 
 
@@ -734,14 +745,14 @@ def main():
         # (enqueues: fq.Head, aq.Tail; dequeues: aq.Head, fq.Tail), and one
         # ticket FAA covers the a lanes of a ticket group taking the same
         # branch (a = group / 2 at a 50/50 mix: 32 for one wavefront, 512
-        # for the default 1024-lane group).  Each successful op performs 2
-        # slot RMWs at the layout's stride.
+        # for the default 1024-lane group).  Each successful op performs
+        # RMW_PER_OP_KIND atomic RMWs at the layout's stride.
         group = args.ticket_group or 1024
         a = group / 2.0
         r_slot = p["r_slot_cas_linear_per_s" if args.slot_mode == "linear" else "r_slot_cas_per_s"]
         per_kernel = {}
         for k in kinds:
-            b = min(2 * a * p["r_ctr_wave_faa_per_s"], r_slot / 2.0,
+            b = min(2 * a * p["r_ctr_wave_faa_per_s"], r_slot / RMW_PER_OP_KIND[k],
                     p["hbm_copy_gbs"] * 1e9 / BYTES_PER_OP_KIND[k])
             per_kernel[NAMES[k]] = {"bound_mops": b / 1e6,
                                     "frac": variants[k]["mops"] * 1e6 / b}

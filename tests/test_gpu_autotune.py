@@ -1,0 +1,24 @@
+"""Autotuner on the device: the chosen configuration is the fastest one it
+measured, and the cache returns it without measuring again."""
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tune_mix_small(tmp_path):
+    from paper_2606_01693_amd import autotune as at
+    path = str(tmp_path / "tune.json")
+    r = at.tune_mix("lfq", 1 << 12, total_ops=1 << 18, ticket_groups=(64, 1024),
+                    lanes_options=(1 << 12, 1 << 13), slot_modes=("linear",), reps=2,
+                    cache_path=path)
+    good = [t for t in r.table if "mops" in t]
+    assert len(good) == 4 and r.best_mops == max(t["mops"] for t in good)
+    assert at.cached(path, r.key).best == r.best
+
+
+def test_tune_multi_small():
+    from paper_2606_01693_amd import autotune as at
+    caps = [1 << e for e in (8, 9, 10, 11, 12, 13, 14, 15)] * 2
+    r = at.tune_multi("lfq", caps, waves_per_256_slots=(0.5, 1, 2), reps=2)
+    assert r.best["waves_per_256_slots"] in (0.5, 1, 2)
+    assert all("mops" in t for t in r.table)
