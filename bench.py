@@ -39,11 +39,13 @@ BYTES_PER_OP = 2 * 16 + 2 * 8 + 2 * 8 + ITEM_BYTES
 # word access (the claim on dequeue, the value check on enqueue) per
 # successful operation, on 32-byte cells.
 BYTES_PER_OP_KIND = {"lfq": BYTES_PER_OP, "wfq": BYTES_PER_OP, "ymc": 32}
-# Atomic read-modify-writes per successful operation (the coalesced RMW rate is
-# the bound once tickets are aggregated): the ring queues install (CAS),
-# consume (XOR) and hand the payload over (exchange); YMC CASes the cell value
-# on an enqueue, and on a dequeue CASes the value and claims the cell.
-RMW_PER_OP_KIND = {"lfq": 3.0, "wfq": 3.0, "ymc": 1.5}
+# Atomic read-modify-writes per successful operation at a 50/50 mix (the
+# coalesced RMW rate is the bound once tickets are aggregated).  Ring queues:
+# an enqueue consumes a free index (XOR), exchanges the payload and installs
+# the index (CAS); a dequeue consumes the index (XOR), loads the payload and
+# installs the index back into the free ring (CAS): (3 + 2) / 2.  YMC: an
+# enqueue CASes the cell value, a dequeue loads it and claims the cell (CAS).
+RMW_PER_OP_KIND = {"lfq": 2.5, "wfq": 2.5, "ymc": 1.0}
 HBM_PEAK_GBS = 8000.0
 
 # Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of the timed kernel, from the

@@ -120,8 +120,11 @@ __device__ __forceinline__ void enq_commit(const Q& y, const Cell& c, uint64_t v
 // are relaxed; request records (value, then state) are published with
 // release and read with acquire.
 __device__ __forceinline__ uint64_t help_enq(const Q& y, Handle* h, const Cell& c, uint64_t i) {
-  uint64_t e = BOT;
-  if (!cas(c.val, e, TOP) && e != TOP) return e;
+  // Look first: a value already in the cell is what the CAS below would
+  // return on failure, and the look is a load instead of a read-modify-write.
+  uint64_t e = ld(c.val);
+  if (e != BOT && e != TOP) return e;
+  if (e == BOT && !cas(c.val, e, TOP) && e != TOP) return e;
   // the cell holds TOP: help a pending slow-path enqueue use this cell
   if (ld_acq(c.enq) == BOT) {
     uint32_t p = 0;
