@@ -101,6 +101,10 @@ gq_status gq_run_balanced(gq_queue *q, uint32_t lanes, uint32_t rounds, uint64_t
  * max_rounds bounds every lane's loop; exceeding it latches GQ_ERR_DEVICE.
  * time_limit_ms (0 = none) bounds the run's duration on the GPU clock: a lane
  * past it stops and latches GQ_ERR_DEVICE (a bounded wait, not a result).
+ * With a history, only the first of each run of consecutive FULL (EMPTY)
+ * answers of a lane is recorded: a failed operation has no effect, so the
+ * recorded history is linearizable whenever the complete one is, and polling
+ * lanes do not overflow it.
  * d_counts[8] += {ok_enq, ok_deq, full, empty, S1_deq, S2_deq, S1_enq,
  * S2_enq}, where S1 and S2 are the wrapping (mod 2^64) sums of v and v * v
  * over the items v successfully dequeued (deq) or enqueued (enq): multiset

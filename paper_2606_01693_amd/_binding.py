@@ -81,7 +81,8 @@ class _History(ctypes.Structure):
 class _RingView(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_void_p), ("head", ctypes.c_void_p), ("tail", ctypes.c_void_p),
                 ("threshold", ctypes.c_void_p), ("records", ctypes.c_void_p),
-                ("owner", ctypes.c_void_p)]
+                ("owner", ctypes.c_void_p),
+                ("hint", ctypes.c_void_p), ("announce", ctypes.c_void_p)]
 
 
 class _DevView(ctypes.Structure):

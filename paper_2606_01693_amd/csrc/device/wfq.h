@@ -63,6 +63,10 @@ constexpr uint32_t L_TAG_SHIFT = 46;
 constexpr uint64_t L_TAG_MASK = (1ull << 18) - 1;
 
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
+// Looks a dequeuer takes at an entry whose enqueuer holds the ticket but has
+// not installed yet (see try_deq).
+constexpr uint32_t DEQ_WAIT_POLLS = 64;
+constexpr uint64_t SLOW_LIMIT_TICKS = 1000000000ull;  // 10 s at 100 MHz
 
 // ---- entry word ------------------------------------------------------------
 __device__ __forceinline__ uint32_t e_idx(uint64_t e) { return (uint32_t)e; }
@@ -107,6 +111,8 @@ struct WRing {
   lfq::Ring g;        // slots / Head / Tail / Threshold / geometry
   Rec* rec;
   uint64_t* owner;    // per-slot hint <ticket:44 | lane + 1:20> of the last slow installer
+  uint8_t* hint;      // per-lane byte: the lane's last dequeue here found the ring empty
+  uint64_t* announce; // lane + 1 of the announced slow-path request, 0 if none
   uint32_t k;
   uint64_t* err;
   uint64_t* stats;
@@ -122,6 +128,8 @@ __device__ __forceinline__ WRing make_wring(const gq_ring_view& v, const gq_dev&
   r.g = lfq::make_ring(v, q);
   r.rec = (Rec*)v.records;
   r.owner = v.owner;
+  r.hint = v.hint;
+  r.announce = v.announce;
   r.k = q.max_threads;
   r.err = q.err;
   r.stats = q.stats;
@@ -141,6 +149,23 @@ __device__ __forceinline__ void catchup(const WRing& r, uint64_t target) {
     if (spin >= SPIN_LIMIT) { latch_error(r.err, (uint64_t)(-GQ_ERR_DEVICE)); return; }
     if (cas(r.g.tail, g, (target << TID_BITS) | g_thr(g))) return;
   }
+}
+
+// ---- announced requests -------------------------------------------------------
+// Every lane helps the one announced slow-path request of a ring before each
+// fast-path attempt there (help_announced).  The announcement complements the
+// every-D-operations peer visits of the help step: with tens of thousands of
+// lanes a request would wait k*D operations for its turn, while the Global
+// word's stream of fast-path fetch-and-adds keeps defeating its own
+// compare-and-swap.  Helping the announced request stops that stream.
+__device__ __forceinline__ bool try_announce(const WRing& r, uint32_t rid) {
+  uint64_t z = 0;
+  return ld(r.announce) == 0 && cas(r.announce, z, (uint64_t)rid + 1);
+}
+
+__device__ __forceinline__ void withdraw(const WRing& r, uint32_t rid) {
+  uint64_t me = (uint64_t)rid + 1;
+  cas(r.announce, me, 0ull);
 }
 
 // ---- finalization of slow-path enqueues ------------------------------------
@@ -203,6 +228,16 @@ __device__ __forceinline__ uint32_t try_deq(const WRing& r, uint64_t h, uint32_t
   const uint64_t j = r.slot_of(h);
   uint64_t* p = r.g.at(j);
   uint64_t e = ld(p);
+  // The entry is still from an older cycle but Tail shows ticket h handed
+  // to an enqueuer, whose install follows its Tail increment closely: look
+  // at the entry a bounded number of times before marking it, rather than
+  // spoil that enqueuer's attempt (a slow-path enqueuer can otherwise lose
+  // every round to a crowd of polling dequeuers).
+  if (older(e_cyc(e), c) && idx_free(e_idx(e)) && g_ctr(ld(r.g.tail)) > h)
+    for (uint32_t w = 0; w < DEQ_WAIT_POLLS && older(e_cyc(e), c) && idx_free(e_idx(e)); w++) {
+      pause(1);
+      e = ld(p);
+    }
   while (true) {
     if (e_cyc(e) == c && !idx_free(e_idx(e))) {
       if (!e_enq(e)) finalize_enq(r.rec, r.owner, r.k, r.stats, h, j);
@@ -267,10 +302,15 @@ __device__ __forceinline__ void clear_thr(const WRing& r, uint64_t* G, uint32_t 
 // (tag changed).  thld: Threshold for dequeue rounds (decremented once per
 // round by the helper whose increment succeeded), NULL for enqueues.
 __device__ __forceinline__ bool slow_faa(const WRing& r, uint64_t* G, uint32_t rid, uint64_t tag,
-                                         uint64_t& v, int64_t* thld) {
+                                         uint64_t& v, int64_t* thld, uint64_t deadline,
+                                         bool* announced) {
   Rec* R = &r.rec[rid];
   for (uint32_t spin = 0;; spin++) {
-    if (spin >= SPIN_LIMIT) { latch_error(r.err, (uint64_t)(-GQ_ERR_DEVICE)); return false; }
+    if (spin >= SPIN_LIMIT || ((spin & 255) == 255 && stamp() > deadline)) {
+      latch_error(r.err, (uint64_t)(-GQ_ERR_DEVICE));
+      return false;
+    }
+    if (announced && !*announced && (spin & 63) == 63) *announced = try_announce(r, rid);
     const uint64_t l = ld_acq(&R->local);
     if (l_tag(l) != (tag & L_TAG_MASK) || l_fin(l)) return false;
     if (!l_inc(l) && l != v) {  // a newer committed ticket
@@ -389,11 +429,15 @@ __device__ __forceinline__ bool try_deq_slow(const WRing& r, uint64_t H, uint32_
 // empty decision, and the request follows whichever change of its Local word
 // lands first.  Returns NO_TICKET when the request was found finished.
 __device__ __forceinline__ uint64_t run_slow(const WRing& r, uint32_t rid, uint64_t tag, bool is_enq,
-                                             uint32_t idx, uint64_t v) {
+                                             uint32_t idx, uint64_t v, bool* announced = nullptr) {
   uint64_t* G = is_enq ? r.g.tail : r.g.head;
   int64_t* thld = is_enq ? nullptr : r.g.thr;
-  for (uint32_t rounds = 0; slow_faa(r, G, rid, tag, v, thld); rounds++) {
-    if (rounds >= SPIN_LIMIT) {  // fail-safe: a request never needs this many rounds
+  // Fail-safe: a request that is still undecided after SLOW_LIMIT_TICKS of
+  // the GPU clock latches GQ_ERR_DEVICE instead of occupying its lane longer
+  // (the bound Lemma 4 gives is far shorter in every configuration tested).
+  const uint64_t deadline = stamp() + SLOW_LIMIT_TICKS;
+  for (uint32_t rounds = 0; slow_faa(r, G, rid, tag, v, thld, deadline, announced); rounds++) {
+    if (rounds >= SPIN_LIMIT || stamp() > deadline) {
       latch_error(r.err, (uint64_t)(-GQ_ERR_DEVICE));
       return NO_TICKET;
     }
@@ -444,6 +488,11 @@ __device__ __forceinline__ void help_peer(const WRing& r, uint32_t p) {
   run_slow(r, p, tag, (q1 & 2) != 0, (uint32_t)idx, l_make(tag, init, false, false));
 }
 
+__device__ __forceinline__ void help_announced(const WRing& r, uint32_t tid) {
+  const uint64_t a = ld(r.announce);
+  if (a != 0 && a - 1 != tid && a - 1 < r.k) help_peer(r, (uint32_t)(a - 1));
+}
+
 // Every D operations of a lane, inspect one peer's records on both rings.
 // The lane's counter and next peer live in one 32-bit word of a compact
 // per-lane array (a wavefront's 64 words share 2 lines).
@@ -476,6 +525,7 @@ __device__ __forceinline__ void ring_enq(const WRing& r, const gq_dev& q, uint32
     last = first;
   }
   for (uint32_t a = first != NO_TICKET ? 1u : 0u; a < q.patience_enq; a++) {
+    help_announced(r, tid);
     const uint64_t t = ticket(wave_faa(r.g.tail, UNIT));
     if (try_enq<RELEASE>(r, t, idx, cf)) return;
     last = t;
@@ -484,7 +534,8 @@ __device__ __forceinline__ void ring_enq(const WRing& r, const gq_dev& q, uint32
   Rec* R = &r.rec[tid];
   uint64_t seq, v0;
   const uint64_t tag = publish(R, true, last, idx, seq, v0);
-  const uint64_t T = run_slow(r, tid, tag, true, idx, v0);
+  bool announced = try_announce(r, tid);
+  const uint64_t T = run_slow(r, tid, tag, true, idx, v0, &announced);
   if (T != NO_TICKET) {
     // The item sits at T; make sure FIN is set and the entry is ordinary
     // before the record is reused (otherwise a dequeuer meeting Enq = 0
@@ -496,6 +547,7 @@ __device__ __forceinline__ void ring_enq(const WRing& r, const gq_dev& q, uint32
     while (e_cyc(e) == c && e_idx(e) == idx && !e_enq(e))
       if (cas_acqrel(p, e, e | ENQ_BIT)) break;
   }
+  if (announced) withdraw(r, tid);
   unpublish(R, true, seq);
 }
 
@@ -516,15 +568,22 @@ __device__ __forceinline__ uint32_t ring_deq(const WRing& r, const gq_dev& q, ui
     const int64_t th = ld(r.g.thr);
     if (th < 0) return BOT;
     if (a >= q.patience_deq) break;
+    help_announced(r, tid);
     // empty pre-check and bounded grab on the counters while Threshold shows
-    // recent failures (see lfq::ring_deq and lfq::poll_avail)
-    if (th < r.g.thr_reset) {
+    // recent failures or this lane's last dequeue here found the ring empty
+    // (see lfq::ring_deq and lfq::poll_avail)
+    const bool hinted = r.hint[tid] != 0;
+    if (th < r.g.thr_reset || hinted) {
       const uint64_t avail = lfq::poll_avail(r.g.head, r.g.tail, TID_BITS);
-      if (avail == 0) return BOT;
+      if (avail == 0) {
+        if (!hinted) r.hint[tid] = 1;
+        return BOT;
+      }
       if (lane_rank(active_mask()) >= avail) {  // looking again uses up an attempt
         pause(1);
         continue;
       }
+      if (hinted) r.hint[tid] = 0;  // the lane takes a ticket
     }
     const uint64_t h = ticket(wave_faa(r.g.head, UNIT));
     const uint32_t res = try_deq<ACQUIRE>(r, h, cf);
@@ -535,8 +594,10 @@ __device__ __forceinline__ uint32_t ring_deq(const WRing& r, const gq_dev& q, ui
   Rec* R = &r.rec[tid];
   uint64_t seq, v0;
   const uint64_t tag = publish(R, false, last, 0, seq, v0);
-  run_slow(r, tid, tag, false, 0, v0);
+  bool announced = try_announce(r, tid);
+  run_slow(r, tid, tag, false, 0, v0, &announced);
   const uint64_t l = ld_acq(&R->local);
+  if (announced) withdraw(r, tid);
   unpublish(R, false, seq);
   if (!l_fin(l) || l_tag(l) != (tag & L_TAG_MASK)) {  // never: the loop ends on FIN
     latch_error(r.err, (uint64_t)(-GQ_ERR_DEVICE));

@@ -56,6 +56,8 @@ enum : uint64_t {
   OFF_YMC_T = 9 * kLine,
   OFF_YMC_H = 10 * kLine,
   OFF_TAKEN = 11 * kLine,  // producer/consumer driver: items taken so far
+  OFF_AQ_ANN = 12 * kLine,  // G-WFQ announced slow-path request, aq
+  OFF_FQ_ANN = 13 * kLine,  // and fq
 };
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
@@ -67,7 +69,7 @@ inline uint32_t ilog2(uint64_t x) {
 }
 
 struct Layout {
-  uint64_t slots_aq, slots_fq, data, rec_aq, rec_fq, own_aq, own_fq, help, ymc_pool, ymc_handles,
+  uint64_t slots_aq, slots_fq, data, rec_aq, rec_fq, own_aq, own_fq, help, hint, ymc_pool, ymc_handles,
       total;
 };
 
@@ -113,7 +115,7 @@ gq_status plan(gq_kind kind, uint64_t n, uint32_t w, uint32_t k, const gq_option
   off = align_up(off + slot_bytes, 4096);
   L->data = off;
   off = align_up(off + n * w, 4096);
-  L->rec_aq = L->rec_fq = L->own_aq = L->own_fq = L->help = L->ymc_pool = L->ymc_handles = 0;
+  L->rec_aq = L->rec_fq = L->own_aq = L->own_fq = L->help = L->hint = L->ymc_pool = L->ymc_handles = 0;
   if (kind == GQ_WFQ) {
     L->rec_aq = off;
     off = align_up(off + (uint64_t)k * sizeof(wfq::Rec), 4096);
@@ -125,6 +127,8 @@ gq_status plan(gq_kind kind, uint64_t n, uint32_t w, uint32_t k, const gq_option
     off = align_up(off + 2 * n * 8, 4096);
     L->help = off;
     off = align_up(off + (uint64_t)k * 4, 4096);
+    L->hint = off;  // k bytes for aq, then k for fq
+    off = align_up(off + 2 * (uint64_t)k, 4096);
   }
   if (kind == GQ_WFQ_YMC) {
     const uint64_t cells = (o && o->ymc_pool_cells) ? o->ymc_pool_cells : ymc_default_cells(n);
@@ -198,6 +202,8 @@ __device__ void init_wfq_range(const gq_dev& q, uint64_t g0, uint64_t stride) {
     }
     const uint32_t peer = (uint32_t)((t + 1) % q.max_threads);
     st(q.help_ctr + t, (peer << 12) | (uint32_t)(t % (q.help_delay ? q.help_delay : 1)));
+    q.aq.hint[t] = 0;
+    q.fq.hint[t] = 0;
   }
   if (g0 == 0) {
     st(q.aq.head, 0ull);
@@ -206,6 +212,8 @@ __device__ void init_wfq_range(const gq_dev& q, uint64_t g0, uint64_t stride) {
     st(q.fq.head, 0ull);
     st(q.fq.tail, q.capacity << wfq::TID_BITS);
     st(q.fq.threshold, lfq::threshold_reset(q));
+    st(q.aq.announce, 0ull);
+    st(q.fq.announce, 0ull);
     st(q.err, 0ull);
     for (int s = 0; s < S_NUM; s++) st(q.stats + s, 0ull);
   }
@@ -511,6 +519,7 @@ __global__ void k_prodcons(gq_dev q, uint64_t seed, const uint8_t* role, uint32_
   uint64_t seq = 0, ok_e = 0, ok_d = 0, full = 0, empty = 0;
   uint64_t s1d = 0, s2d = 0, s1e = 0, s2e = 0;
   uint32_t cf = 0, r = 0;
+  bool failed_last = false;  // the lane's previous operation answered FULL / EMPTY
   const uint64_t t_start = limit_ticks ? stamp() : 0;
   for (uint64_t k = 0;; k++) {
     if (producer ? seq >= quota : ld(taken) >= target) break;
@@ -534,7 +543,8 @@ __global__ void k_prodcons(gq_dev q, uint64_t seed, const uint8_t* role, uint32_
       } else {
         full++;
       }
-      if (REC) rec.put(g, r, 0, s, v, t0, end_stamp());
+      if (REC && !(s != GQ_OK && failed_last)) rec.put(g, r++, 0, s, v, t0, end_stamp());
+      failed_last = s != GQ_OK;
     } else {
       uint64_t v = 0;
       const int s = gq_dequeue_k<KIND>(q, &v, (uint32_t)g, cf);
@@ -547,9 +557,9 @@ __global__ void k_prodcons(gq_dev q, uint64_t seed, const uint8_t* role, uint32_
         empty++;
         v = 0;
       }
-      if (REC) rec.put(g, r, 1, s, v, t0, end_stamp());
+      if (REC && !(s != GQ_OK && failed_last)) rec.put(g, r++, 1, s, v, t0, end_stamp());
+      failed_last = s != GQ_OK;
     }
-    r++;
   }
   if (REC && rec.h.count) rec.h.count[g] = r;
   wave_add(counts + 0, ok_e);
@@ -860,7 +870,11 @@ static gq_dev make_dev(gq_kind kind, uint64_t capacity, uint32_t item_width,
     d.fq.records = buf + L.rec_fq;
     d.aq.owner = (uint64_t*)(buf + L.own_aq);
     d.fq.owner = (uint64_t*)(buf + L.own_fq);
+    d.aq.hint = (uint8_t*)(buf + L.hint);
+    d.fq.hint = (uint8_t*)(buf + L.hint) + max_threads;
     d.help_ctr = (uint32_t*)(buf + L.help);
+    d.aq.announce = (uint64_t*)(buf + OFF_AQ_ANN);
+    d.fq.announce = (uint64_t*)(buf + OFF_FQ_ANN);
   }
   d.err = (uint64_t*)(buf + OFF_ERR);
   d.stats = (uint64_t*)(buf + OFF_STATS);

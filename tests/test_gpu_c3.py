@@ -65,25 +65,19 @@ def c3_run(kind, n, waves, prod_waves, log2_inv_p, items, seed, hist_per_lane=0,
     return q, role, quota, target, c, h
 
 
-# G-WFQ at full size is skipped: its first run (128 producer and 896 consumer
-# wavefronts, p = 1) made no progress visible for three minutes.  The reading
-# is that the 57,344 polling consumers burn the slots of the producers'
-# tickets, the producers fall into the slow path together, and its ticket CAS
-# then competes with tens of thousands of fast-path FAAs, progressing only
-# through helping (a bound that grows with D * k).  Until that is shown and
-# addressed, the case stays off the GPU.
-FULL_SIZE_KINDS = [pytest.param(k, marks=pytest.mark.skip(
-    reason="G-WFQ at 65,536 lanes with 7:1 polling consumers: slow-path helping "
-           "storm under investigation")) if k == "wfq" else k for k in KINDS]
-
-
-@pytest.mark.parametrize("kind", FULL_SIZE_KINDS)
+@pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("prod_waves", [128, 512, 896])
 @pytest.mark.parametrize("log2_inv_p", [0, 1, 6])
 def test_c3_full_size_conservation(kind, prod_waves, log2_inv_p):
     if kind == "ymc" and prod_waves == 128:
         pytest.skip("G-WFQ-YMC takes a cell per empty poll: 57,344 polling consumers exhaust "
                     "even 2^30 cells (its memory is not bounded, Section III-A)")
+    if kind == "wfq" and (prod_waves == 128 or log2_inv_p == 6):
+        pytest.skip("G-WFQ with 57,344 polling consumers, or with one lane in 64 active per "
+                    "round: slow-path requests outlast the 10 s fail-safe bound now and then "
+                    "(each such request ends with GQ_ERR_DEVICE and drops its operation); "
+                    "measured 8,388,055 of 8,388,608 items at p = 1/2 and 1.8 M at p = 1/64 "
+                    "in 20 s")
     T = torch()
     seed = workloads.run_seed(3, prod_waves + log2_inv_p)
     q, role, quota, target, c, _ = c3_run(kind, 1 << 16, 1024, prod_waves, log2_inv_p,
@@ -107,10 +101,6 @@ def test_c3_full_size_conservation(kind, prod_waves, log2_inv_p):
 @pytest.mark.parametrize("log2_inv_p", [0, 6])
 def test_c3_shape_histories(kind, prod_waves, log2_inv_p):
     """64 wavefronts, capacity 2^10, 2^15 items, whole history recorded."""
-    if kind == "wfq":
-        pytest.skip("G-WFQ with 7:1 polling: at 4096 lanes (8:56) a lane stayed in the slow "
-                    "path for minutes; its Global-word CAS loses to the pollers' fast-path "
-                    "FAAs until helping reaches it (see the full-size skip)")
     if kind == "ymc" and prod_waves == 8:
         pytest.skip("G-WFQ-YMC takes a cell per empty poll: 56 polling consumer wavefronts "
                     "exhaust its pool (its memory is not bounded, Section III-A)")
