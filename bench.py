@@ -55,14 +55,15 @@ KERNEL_SOURCES = ("paper_2606_01693_amd/csrc/device/common.h",
                   "paper_2606_01693_amd/csrc/device/lfq.h",
                   "paper_2606_01693_amd/csrc/device/wfq.h",
                   "paper_2606_01693_amd/csrc/device/ymc.h",
-                  "paper_2606_01693_amd/csrc/gq_lib.hip")
+                  "paper_2606_01693_amd/csrc/gq_lib.hip",
+                  "include/gq.h", "include/gq_device.h")
 _PROFILE = "profiles/k_mix_group_mixed5050_cap2p20_ops2p26.md"
 TRAFFIC_PROFILE = {  # kind -> scaled FETCH_SIZE + WRITE_SIZE bytes per launch of the step kernel
-    "lfq": {"sources_sha256_16": "5acb8e63d97b1247", "bytes_per_launch": 4.007e9,
+    "lfq": {"sources_sha256_16": "40a7705784592c0c", "bytes_per_launch": 4.008e9,
             "profile": _PROFILE},
-    "wfq": {"sources_sha256_16": "5acb8e63d97b1247", "bytes_per_launch": 4.205e9,
+    "wfq": {"sources_sha256_16": "40a7705784592c0c", "bytes_per_launch": 4.199e9,
             "profile": _PROFILE},
-    "ymc": {"sources_sha256_16": "5acb8e63d97b1247", "bytes_per_launch": 3.482e9,
+    "ymc": {"sources_sha256_16": "40a7705784592c0c", "bytes_per_launch": 3.096e9,
             "profile": _PROFILE},
 }
 NAMES = {"lfq": "G-LFQ", "wfq": "G-WFQ", "ymc": "G-WFQ-YMC"}
