@@ -151,11 +151,18 @@ __device__ __forceinline__ uint64_t help_enq(const Q& y, Handle* h, const Cell& 
   Handle* r = &y.hd[ce - 1];
   const uint64_t s = ld_acq(&r->enq_state);
   const uint64_t v = ld_acq(&r->enq_val);
-  if ((s & ID_MASK) > i) {
-    // the request started after this cell: it cannot use it
+  if ((s & PENDING) && (s & ID_MASK) > i) {
+    // a pending request that started after this cell cannot use it
     if (ld(c.val) == TOP && ld(y.T) <= i) return RES_EMPTY;
-  } else if (try_claim(&r->enq_state, s & ID_MASK, i) || (s == i && ld(c.val) == TOP)) {
-    enq_commit(y, c, v, i);
+  } else {
+    // Claim the pending request for cell i.  A failed claim leaves the state
+    // it met in cur: if that is a claim for cell i (made by the request's
+    // owner or another helper, whose value store may still be on its way),
+    // the value is stored here too, so this dequeuer does not leave cell i
+    // for a value that lands after it moved on.
+    uint64_t cur = s;
+    const bool claimed = (s & PENDING) && cas_acqrel(&r->enq_state, cur, i);
+    if (claimed || (cur == i && ld(c.val) == TOP)) enq_commit(y, c, v, i);
   }
   return ld_acq(c.val);
 }
