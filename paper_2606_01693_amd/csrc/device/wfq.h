@@ -66,6 +66,7 @@ constexpr uint32_t SPIN_LIMIT = 1u << 22;
 // Looks a dequeuer takes at an entry whose enqueuer holds the ticket but has
 // not installed yet (see try_deq).
 constexpr uint32_t DEQ_WAIT_POLLS = 64;
+constexpr uint32_t DEQ_WAIT_POLLS_SLOW = 2048;
 constexpr uint64_t SLOW_LIMIT_TICKS = 1000000000ull;  // 10 s at 100 MHz
 
 // ---- entry word ------------------------------------------------------------
@@ -233,11 +234,15 @@ __device__ __forceinline__ uint32_t try_deq(const WRing& r, uint64_t h, uint32_t
   // at the entry a bounded number of times before marking it, rather than
   // spoil that enqueuer's attempt (a slow-path enqueuer can otherwise lose
   // every round to a crowd of polling dequeuers).
-  if (older(e_cyc(e), c) && idx_free(e_idx(e)) && g_ctr(ld(r.g.tail)) > h)
-    for (uint32_t w = 0; w < DEQ_WAIT_POLLS && older(e_cyc(e), c) && idx_free(e_idx(e)); w++) {
+  // A slow-path install takes longer (SlowFAA's two phases, helpers): while
+  // a slow-path request is announced on the ring the wait is longer too.
+  if (older(e_cyc(e), c) && idx_free(e_idx(e)) && g_ctr(ld(r.g.tail)) > h) {
+    const uint32_t polls = ld(r.announce) ? DEQ_WAIT_POLLS_SLOW : DEQ_WAIT_POLLS;
+    for (uint32_t w = 0; w < polls && older(e_cyc(e), c) && idx_free(e_idx(e)); w++) {
       pause(1);
       e = ld(p);
     }
+  }
   while (true) {
     if (e_cyc(e) == c && !idx_free(e_idx(e))) {
       if (!e_enq(e)) finalize_enq(r.rec, r.owner, r.k, r.stats, h, j);
@@ -490,7 +495,12 @@ __device__ __forceinline__ void help_peer(const WRing& r, uint32_t p) {
 
 __device__ __forceinline__ void help_announced(const WRing& r, uint32_t tid) {
   const uint64_t a = ld(r.announce);
-  if (a != 0 && a - 1 != tid && a - 1 < r.k) help_peer(r, (uint32_t)(a - 1));
+  if (a == 0 || a - 1 == tid || a - 1 >= r.k) return;
+  // One helper per wavefront: the wavefront waits while its first lane
+  // helps, which already keeps its fetch-and-adds off the Global word, and
+  // a request with tens of thousands of helpers would spend its rounds on
+  // their CAS traffic to its Local and Global words.
+  if (lane_rank(active_mask()) == 0) help_peer(r, (uint32_t)(a - 1));
 }
 
 // Every D operations of a lane, inspect one peer's records on both rings.

@@ -438,8 +438,11 @@ def test_wfq_tiny_histories_slow_path(chunk):
 # ---------------------------------------------------------------------------
 # G-WFQ-YMC slow path, forced (patience 0), and the pool-exhaustion latch.
 # ---------------------------------------------------------------------------
+# (the 16384-lane case races slow-path enqueue claims against dequeuers
+# marking the same cells, where a helper must commit a claim it lost to the
+# owner for its own cell)
 @pytest.mark.parametrize("n,lanes,ops,patience", [(64, 1024, 16, 0), (1 << 10, 4096, 16, 1),
-                                                   (16, 2048, 16, 0)])
+                                                   (16, 2048, 16, 0), (1 << 10, 16384, 32, 1)])
 @pytest.mark.parametrize("tg", TICKET_GROUPS)
 def test_ymc_forced_slow_path_mix(n, lanes, ops, patience, tg):
     run_mix_checked("ymc", n, lanes, ops, workloads.run_seed(4, n + patience), patience=patience,
