@@ -59,11 +59,11 @@ KERNEL_SOURCES = ("paper_2606_01693_amd/csrc/device/common.h",
                   "include/gq.h", "include/gq_device.h")
 _PROFILE = "profiles/k_mix_group_mixed5050_cap2p20_ops2p26.md"
 TRAFFIC_PROFILE = {  # kind -> scaled FETCH_SIZE + WRITE_SIZE bytes per launch of the step kernel
-    "lfq": {"sources_sha256_16": "40a7705784592c0c", "bytes_per_launch": 4.008e9,
+    "lfq": {"sources_sha256_16": "1733de1121d73770", "bytes_per_launch": 4.009e9,
             "profile": _PROFILE},
-    "wfq": {"sources_sha256_16": "40a7705784592c0c", "bytes_per_launch": 4.199e9,
+    "wfq": {"sources_sha256_16": "1733de1121d73770", "bytes_per_launch": 4.199e9,
             "profile": _PROFILE},
-    "ymc": {"sources_sha256_16": "40a7705784592c0c", "bytes_per_launch": 3.096e9,
+    "ymc": {"sources_sha256_16": "1733de1121d73770", "bytes_per_launch": 3.097e9,
             "profile": _PROFILE},
 }
 NAMES = {"lfq": "G-LFQ", "wfq": "G-WFQ", "ymc": "G-WFQ-YMC"}
