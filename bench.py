@@ -67,6 +67,20 @@ TRAFFIC_PROFILE = {  # kind -> scaled FETCH_SIZE + WRITE_SIZE bytes per launch o
             "profile": _PROFILE},
 }
 NAMES = {"lfq": "G-LFQ", "wfq": "G-WFQ", "ymc": "G-WFQ-YMC"}
+# The paper's per-operation profile metrics (VALU/op, WAIT/op) and L2 atomic
+# requests per operation of the step kernels, from the rocprofv3 SQ_* and
+# TCC_ATOMIC_sum runs summarised in the named profile; reported under the
+# same conditions as the traffic figure.
+_COUNTERS = "profiles/k_mix_group_mixed5050_sq_tcc_counters.md"
+COUNTER_PROFILE = {
+    "lfq": {"valu_per_op": 3.08, "wait_frac": 0.780, "wait_per_op": 1.16e-8,
+            "tcc_atomic_per_op": 0.571},
+    "wfq": {"valu_per_op": 6.44, "wait_frac": 0.762, "wait_per_op": 1.14e-8,
+            "tcc_atomic_per_op": 0.570},
+    "ymc": {"valu_per_op": 1.87, "wait_frac": 0.875, "wait_per_op": 1.30e-8,
+            "tcc_atomic_per_op": 0.276},
+}
+COUNTER_SOURCES_HASH = "1733de1121d73770"
 
 
 def kernel_sources_hash() -> str:
@@ -744,6 +758,10 @@ def main():
             "bytes_per_ok_op": bpo,
         },
     }
+    if (kernel_sources_hash() == COUNTER_SOURCES_HASH and args.ticket_group in (0, 1024)
+            and args.slot_mode == "linear" and not args.fenced):
+        out["profile_counters"] = {NAMES[k]: COUNTER_PROFILE[k] for k in kinds}
+        out["profile_counters"]["profile"] = _COUNTERS
     if not args.no_probes:
         p = measure_probes(gq, torch)
         # Each of the four ticket counters serves one of every two operations
