@@ -1,14 +1,15 @@
 """MI355X-native concurrent FIFO queues (G-LFQ, G-WFQ, G-WFQ-YMC) for gfx950.
 
 The queues are hand-written HIP in csrc/, exported through the C ABI of
-include/gq.h, include/gq_bench.h and include/gq_serve.h (libgq.so).  This package is the thin
+include/gq.h, include/gq_bench.h, include/gq_serve.h and include/gq_rt.h (libgq.so).  This package is the thin
 ctypes binding; importing it loads libgq.so and fails loudly when it is not
 built.
 """
 from ._binding import (  # noqa: F401
     EXPORTS, GQ_EMPTY, GQ_ERR_CYCLE_BOUND, GQ_ERR_DEVICE, GQ_ERR_HIP, GQ_ERR_INVALID,
     GQ_ERR_NOMEM, GQ_ERR_POOL_EXHAUSTED, GQ_ERR_RESIDENCY, GQ_FULL, GQ_OK, KINDS, GQError,
-    SERVE_HASH_SEED, History, Multi, Queue, Server, Stats, bfs, device_info, lib, probe_cas,
+    RT_COMPACT, RT_QUEUES, SERVE_HASH_SEED, History, Multi, Queue, RayTracer, Server, Stats, bfs,
+    device_info, lib, probe_cas,
     probe_copy, probe_faa, probe_fence, required_bytes, resident_blocks, status_str,
 )
 

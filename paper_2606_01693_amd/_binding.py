@@ -23,7 +23,7 @@ GQ_ERR_CYCLE_BOUND, GQ_ERR_POOL_EXHAUSTED, GQ_ERR_DEVICE = -5, -6, -7
 KINDS = {"lfq": 0, "wfq": 1, "ymc": 2}
 SLOT_MODES = {"remap": 0, "padded": 1, "linear": 2}
 
-# Every symbol include/gq.h and include/gq_bench.h declare.
+# Every symbol the headers under include/ declare.
 EXPORTS = (
     "gq_required_bytes", "gq_create", "gq_destroy", "gq_reset", "gq_enqueue_batch",
     "gq_dequeue_batch", "gq_device_view", "gq_read_stats", "gq_clear_stats",
@@ -32,7 +32,7 @@ EXPORTS = (
     "gq_resident_blocks", "gq_device_info", "gq_multi_create", "gq_multi_run_mix",
     "gq_multi_capture", "gq_multi_replay", "gq_multi_destroy", "gq_bfs",
     "gq_serve_create", "gq_serve_run", "gq_serve_job_bytes", "gq_serve_destroy",
-    "gq_run_timed",
+    "gq_run_timed", "gq_rt_create", "gq_rt_render", "gq_rt_check_error", "gq_rt_destroy",
 )
 
 
@@ -140,6 +140,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gq_serve_run": [P, U32, P, P, U32, P],
         "gq_serve_job_bytes": [P, U32, U64, P],
         "gq_serve_destroy": [P],
+        "gq_rt_create": [I32, U32, U32, U32, U32, P],
+        "gq_rt_render": [P, P, U32, P, P, P, P],
+        "gq_rt_check_error": [P, P],
+        "gq_rt_destroy": [P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -547,3 +551,77 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ---- tile-based wavefront ray tracer (include/gq_rt.h) ----------------------
+RT_QUEUES, RT_COMPACT = 0, 1
+RT_MAX_SPHERES, RT_MAX_PLANES = 128, 8
+
+
+class _RtScene(ctypes.Structure):
+    _fields_ = [("spheres", ctypes.c_void_p), ("planes", ctypes.c_void_p),
+                ("n_spheres", ctypes.c_uint32), ("n_planes", ctypes.c_uint32),
+                ("camera", ctypes.c_float * 7), ("light", ctypes.c_float * 3),
+                ("shade", ctypes.c_float * 2), ("background", ctypes.c_float * 3),
+                ("max_bounces", ctypes.c_uint32)]
+
+
+class RayTracer:
+    """Per-tile queues of `kind` over a width x height image (gq_rt_create ..
+    gq_rt_destroy).  ``render(scene)`` takes a scene dict of float32 arrays
+    (the layout gq_rt.h documents) and returns (image [h*w, 3] float32,
+    segments [h*w] int32, stats [4] int64) as device tensors."""
+
+    def __init__(self, kind: str, width: int, height: int, tile: int = 32, lanes: int = 8192):
+        self.width, self.height, self.kind = width, height, kind
+        h = ctypes.c_void_p(0)
+        _check(lib().gq_rt_create(KINDS[kind], width, height, tile, lanes, ctypes.byref(h)),
+               "gq_rt_create")
+        self._h = h
+        self._scene_keep = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gq_rt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_scene(self, scene: dict):
+        torch = _torch()
+        sph = torch.as_tensor(scene["spheres"], dtype=torch.float32).reshape(-1).contiguous().cuda()
+        pl = torch.as_tensor(scene["planes"], dtype=torch.float32).reshape(-1).contiguous().cuda()
+        sc = _RtScene()
+        sc.spheres = sph.data_ptr() if sph.numel() else None
+        sc.planes = pl.data_ptr() if pl.numel() else None
+        sc.n_spheres = len(scene["spheres"])
+        sc.n_planes = len(scene["planes"])
+        for name, n in (("camera", 7), ("light", 3), ("shade", 2), ("background", 3)):
+            arr = getattr(sc, name)
+            for i in range(n):
+                arr[i] = float(scene[name][i])
+        sc.max_bounces = int(scene["max_bounces"])
+        self._scene_keep = (sph, pl)
+        self._scene = sc
+
+    def render(self, method: int = RT_QUEUES, image=None, segments=None, stats=None, stream=None):
+        torch = _torch()
+        n = self.width * self.height
+        if image is None:
+            image = torch.empty(n * 3, dtype=torch.float32, device="cuda")
+        if segments is None:
+            segments = torch.empty(n, dtype=torch.int32, device="cuda")
+        if stats is None:
+            stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+        if image.numel() < n * 3 or segments.numel() < n or stats.numel() < 4:
+            raise ValueError("render: output buffers too small")
+        _check(lib().gq_rt_render(self._h, ctypes.byref(self._scene), method, _ptr(image),
+                                  _ptr(segments), _ptr(stats), _stream(stream)), "gq_rt_render")
+        return image.view(n, 3), segments, stats
+
+    def check_error(self, stream=None) -> int:
+        return int(lib().gq_rt_check_error(self._h, _stream(stream)))

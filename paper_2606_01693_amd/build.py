@@ -13,6 +13,9 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions stay off in every HIP build of this project
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # float32 expressions (the ray tracer) are evaluated as written: no
+    # contraction into fused multiply-adds
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-function",
 ]
 

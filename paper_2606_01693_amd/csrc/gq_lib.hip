@@ -1450,3 +1450,4 @@ gq_status gq_bfs(gq_queue* qa, gq_queue* qb, const uint32_t* d_offsets, const ui
 }
 
 #include "gq_serve.inc"
+#include "gq_rt.inc"

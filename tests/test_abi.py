@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_2606_01693_amd", "libgq.so")
 
 def declared_functions():
     names = set()
-    for h in ("gq.h", "gq_bench.h", "gq_serve.h"):
+    for h in ("gq.h", "gq_bench.h", "gq_serve.h", "gq_rt.h"):
         text = open(os.path.join(ROOT, "include", h)).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
         for m in re.finditer(r"\b(gq_[a-z_0-9]+)\s*\(", text):
@@ -121,3 +121,22 @@ def test_device_view_struct_matches_header():
     assert names[-1] == "ticket_group"
     dev = [f[0] for f in b._DevView._fields_]
     assert dev[dev.index("help_delay") + 1] == "group_lanes"
+
+
+@pytest.mark.parametrize("kind,w,h,tile,lanes", [
+    (2, 64, 64, 32, 8192),      # G-WFQ-YMC is not offered for the tracer
+    (0, 0, 64, 32, 8192),       # empty image
+    (0, 64, 64, 24, 8192),      # tile not in {8, 16, 32, 64}
+    (0, 64, 64, 32, 1000),      # lanes not a multiple of 256
+    (0, 64, 64, 32, 0),
+    (1, 64, 64, 32, 1 << 21),   # too many lanes
+])
+def test_rt_create_rejects_bad_arguments(kind, w, h, tile, lanes):
+    """gq_rt_create validates its arguments before touching the device."""
+    from paper_2606_01693_amd import _binding as b
+    L = b.load_library()
+    out = ctypes.c_void_p(0)
+    assert L.gq_rt_create(kind, w, h, tile, lanes, ctypes.byref(out)) == b.GQ_ERR_INVALID
+    assert out.value is None
+    assert L.gq_rt_render(None, None, 0, None, None, None, None) == b.GQ_ERR_INVALID
+    assert L.gq_rt_destroy(None) == b.GQ_ERR_INVALID
