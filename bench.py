@@ -390,6 +390,58 @@ def serve_level_hash(levels: np.ndarray, seed: int) -> int:
         return int((w * (levels.astype(np.uint64) + np.uint64(1))).sum(dtype=np.uint64))
 
 
+RT_SIZE = (1920, 1080)
+RT_LANES = (1 << 9, 1 << 11, 1 << 13, 1 << 15)
+
+
+def bench_rt(gq, torch, reps=5):
+    """Tile-based wavefront ray tracing (1920 x 1080, 32 x 32 tiles): MRays/s
+    = path segments traced / render time (median of `reps` after a warmup),
+    for per-tile G-LFQ and G-WFQ queues and for stream compaction, at lane
+    counts 2^9 .. 2^15.  Every image is compared bit for bit with the
+    compaction image of the same scene."""
+    from workloads import scenes
+    w, h = RT_SIZE
+    out = {}
+    for name in ("complex", "cornell"):
+        sc = (scenes.complex_scene(20260601, w, h) if name == "complex"
+              else scenes.cornell_scene(w, h))
+        res, ref_img = {}, None
+        for method, kind in (("compact", "lfq"), ("G-LFQ", "lfq"), ("G-WFQ", "wfq")):
+            for lanes in RT_LANES:
+                r = gq.RayTracer(kind, w, h, tile=32, lanes=lanes)
+                r.set_scene(sc)
+                m = gq.RT_COMPACT if method == "compact" else gq.RT_QUEUES
+                img, segs, stats = r.render(m)
+                ms = []
+                for _ in range(reps):
+                    e0, e1 = _events(torch)
+                    e0.record()
+                    r.render(m, img, segs, stats)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    ms.append(e0.elapsed_time(e1))
+                err = r.check_error()
+                st = stats.cpu().tolist()
+                bits = img.cpu().numpy().view(np.uint32)
+                if ref_img is None:
+                    ref_img = bits.copy()
+                med = float(np.median(ms))
+                res[f"{method} lanes={lanes}"] = {
+                    "ms": med, "mrays_s": st[0] / (med * 1e-3) / 1e6, "segments": st[0],
+                    "empty_polls": st[2], "ok": bool(err == 0 and np.array_equal(bits, ref_img))}
+                log(f"[bench] rt {name} {method} lanes={lanes}: {med:.2f} ms, "
+                    f"{res[f'{method} lanes={lanes}']['mrays_s']:.0f} MRays/s, ok={err == 0}")
+                r.close()
+        best_c = max(v["mrays_s"] for k, v in res.items() if k.startswith("compact"))
+        same = {k: v["mrays_s"] / res["compact lanes=" + k.split("lanes=")[1]]["mrays_s"]
+                for k, v in res.items()}
+        out[name] = {"runs": res, "best_compact_mrays_s": best_c,
+                     "relative_to_compact_same_lanes": same,
+                     "relative_to_best_compact": {k: v["mrays_s"] / best_c for k, v in res.items()}}
+    return out
+
+
 def bench_serve(gq, torch, njobs=1000, pool_size=64, team_lanes=1024, budget=16 << 30):
     """Serving: a pool of 64 R-MAT graphs (scale uniform in 12..20, edge
     factor 16, seeded), 1000 BFS jobs each on a graph drawn from the pool,
@@ -628,6 +680,7 @@ def main():
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-rt", action="store_true")
     ap.add_argument("--no-c2", action="store_true")
     ap.add_argument("--no-timed", action="store_true")
     ap.add_argument("--ticket-group", type=int, default=0,
@@ -802,6 +855,8 @@ def main():
         out["bfs"] = bench_bfs(gq, torch)
     if not args.no_serve:
         out["serve"] = bench_serve(gq, torch)
+    if not args.no_rt:
+        out["raytrace"] = bench_rt(gq, torch)
     if not args.no_cpu:
         replay, locked = cpu_baselines(base_seed, LANES)
         out["cpu_baseline"] = replay

@@ -1,11 +1,12 @@
 /* gq_rt.h -- tile-based wavefront ray tracer driven by the device queues.
  *
  * The paper's ray-tracing workload (Section V-B, tile-based wavefront ray
- * tracing; results in Section VI, wavefront ray tracing with concurrent
- * queues): a W x H image is cut into square tiles, each tile owns one queue,
- * primary rays are enqueued per tile, and a persistent kernel dequeues work,
- * traces and shades one path segment, and re-enqueues the reflective bounce
- * into the same tile's queue until no work remains.  It is compared with a
+ * tracing; results in Section VI-E): a W x H image is cut into square tiles,
+ * each tile owns one queue, primary rays are enqueued per tile, and a
+ * persistent kernel dequeues work, traces and shades one path segment, and
+ * re-enqueues the reflective bounce into the same tile's queue until no work
+ * remains.  Here a wavefront claims one tile at a time from a global cursor
+ * and works its queue until a dequeue of all its lanes finds it empty.  It is compared with a
  * stream-compaction tracer that gathers the surviving rays into a dense list
  * between passes, one launch per bounce depth.
  *
