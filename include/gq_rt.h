@@ -6,9 +6,9 @@
  * persistent kernel dequeues work, traces and shades one path segment, and
  * re-enqueues the reflective bounce into the same tile's queue until no work
  * remains.  Here a wavefront claims one tile at a time from a global cursor
- * and works its queue until a dequeue of all its lanes finds it empty.  It is compared with a
- * stream-compaction tracer that gathers the surviving rays into a dense list
- * between passes, one launch per bounce depth.
+ * and works its queue until a dequeue of all its lanes finds it empty.  It is
+ * compared with a stream-compaction tracer that gathers the surviving rays
+ * into a dense list between passes, one launch per bounce depth.
  *
  * What is traced (both methods compute the same bits per pixel): the path of
  * each pixel, segment by segment, in float32, each operation rounded in a
