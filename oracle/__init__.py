@@ -178,13 +178,14 @@ def producer_order(h: History, shift: int = 32):
 # ----------------------------------------------------------------------------
 # O6 violation scan
 # ----------------------------------------------------------------------------
-VIOLATIONS = ("fresh", "repeat", "order", "witness", "witness_count", "full", "loss")
+VIOLATIONS = ("fresh", "repeat", "order", "witness", "witness_count", "full", "loss",
+              "witness_union")
 
 
 def violation_scan(h: History, prefill=(), drain=(), capacity: int = 0):
     pre = _u64(prefill)
     dr = _u64(drain)
-    out = np.zeros(7, dtype=np.uint64)
+    out = np.zeros(len(VIOLATIONS), dtype=np.uint64)
     rc = lib().orc_violation_scan(len(h), _p(h.op), _p(h.st), _p(h.val), _p(h.call),
                                   _p(h.ret), pre.shape[0], _p(pre), dr.shape[0], _p(dr),
                                   capacity, _p(out))

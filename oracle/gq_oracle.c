@@ -263,7 +263,12 @@ int orc_producer_order(uint64_t m, const uint32_t *proc, const uint8_t *op,
 /*               enqueues exceeded the count of possibly started dequeues;    */
 /*   [5] VFull   a FULL enqueue ran while the queue could never have held    */
 /*               `capacity` items (capacity 0 disables this check);          */
-/*   [6] VLoss   a value was enqueued and never dequeued nor drained.         */
+/*   [6] VLoss   a value was enqueued and never dequeued nor drained;         */
+/*   [7] VWitU   an EMPTY dequeue ran while, at every instant of it, some     */
+/*               value was certainly in the queue: the open intervals         */
+/*               (enqueue end, dequeue call) of the values cover the EMPTY's  */
+/*               whole [call, end], though no single one may (this finds      */
+/*               EMPTY answers that VWit and VWitN miss).                     */
 /* Prefill values count as enqueued, in order, before the history; drained  */
 /* values count as dequeued, in order, after it.                             */
 /* Returns 0 iff every count is zero.                                         */
@@ -340,7 +345,7 @@ int orc_violation_scan(uint64_t m, const uint8_t *op, const uint8_t *st,
                        const uint64_t *drain, uint64_t capacity,
                        uint64_t *counts)
 {
-    for (int c = 0; c < 7; c++) counts[c] = 0;
+    for (int c = 0; c < 8; c++) counts[c] = 0;
 
     /* Map stamps to one signed time line: prefill item k occupies the      */
     /* instant 2k+1, the history starts after all of them, and drain item k */
@@ -434,6 +439,37 @@ int orc_violation_scan(uint64_t m, const uint8_t *op, const uint8_t *st,
         }
     qsort(qs, nq, sizeof(iv_t), cmp_iv_t0);
     counts[3] = sweep_present(by_ee, n_enq, qs, nq);
+
+    /* VWitU: merge the values' open presence intervals (ee, dc) -- sorted   */
+    /* by ee in by_ee -- into disjoint segments; an EMPTY [t0, t1] is a hit  */
+    /* when one segment (a, b) has a < t0 and t1 < b.  Two intervals merge   */
+    /* only when they overlap (a shared end point is an uncovered instant).  */
+    {
+        iv_t *seg = (iv_t *)malloc((n_enq + 1) * sizeof(iv_t));
+        if (!seg) { free(E); free(D); free(by_ee); free(qs); return -1; }
+        uint64_t ns = 0;
+        for (uint64_t k = 0; k < n_enq; k++) {
+            const int64_t a = by_ee[k].t, b = by_ee[k].v;
+            if (b <= a) continue;
+            if (ns > 0 && a < seg[ns - 1].t1) {
+                if (b > seg[ns - 1].t1) seg[ns - 1].t1 = b;
+            } else {
+                seg[ns].t0 = a;
+                seg[ns].t1 = b;
+                ns++;
+            }
+        }
+        for (uint64_t q = 0; q < nq; q++) {
+            /* last segment with t0 < query start */
+            uint64_t lo = 0, hi = ns;
+            while (lo < hi) {
+                const uint64_t mid = (lo + hi) / 2;
+                if (seg[mid].t0 < qs[q].t0) lo = mid + 1; else hi = mid;
+            }
+            if (lo > 0 && seg[lo - 1].t1 > qs[q].t1) counts[7]++;
+        }
+        free(seg);
+    }
 
     /* VWitN and VFull use counts of stamps. */
     int64_t *enq_end = (int64_t *)malloc((n_enq + 1) * sizeof(int64_t));

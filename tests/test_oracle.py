@@ -342,6 +342,29 @@ def test_scan_catalogue_patterns():
             assert oracle.all_zero(scan(rows)), rows
 
 
+def test_scan_union_witness():
+    """EMPTY over [4, 10]: value 1 is certainly present on (1, 7), value 2 on
+    (5, 12).  Neither covers the EMPTY alone and the count bound is 0, but
+    together they cover it: not linearizable (the exhaustive search agrees),
+    and only the union witness finds it.  With value 2's enqueue ending at 8
+    the instant 7.5 is uncovered and the history is legal."""
+    rows = [(0, OP_ENQ, ST_OK, 1, 0, 1), (1, OP_ENQ, ST_OK, 2, 2, 5),
+            (2, OP_DEQ, ST_EMPTY, 0, 4, 10), (3, OP_DEQ, ST_OK, 1, 7, 8),
+            (4, OP_DEQ, ST_OK, 2, 12, 13)]
+    r = scan(rows)
+    assert r["witness_union"] == 1 and r["witness"] == 0 and r["witness_count"] == 0
+    assert sum(r.values()) == 1
+    assert not check_linearizable(rows)[0]
+    legal = [(0, OP_ENQ, ST_OK, 1, 0, 1), (1, OP_ENQ, ST_OK, 2, 2, 8),
+             (2, OP_DEQ, ST_EMPTY, 0, 4, 10), (3, OP_DEQ, ST_OK, 1, 7, 8),
+             (4, OP_DEQ, ST_OK, 2, 12, 13)]
+    assert oracle.all_zero(scan(legal))
+    assert check_linearizable(legal)[0]
+    # a value never dequeued covers to +infinity; a drained one up to its drain
+    rows = [(0, OP_ENQ, ST_OK, 1, 0, 1), (2, OP_DEQ, ST_EMPTY, 0, 4, 10)]
+    assert scan(rows, drain=[1])["witness_union"] == 1
+
+
 def test_scan_spurious_full():
     # capacity 2: one item in the queue, FULL answered: impossible
     rows = [(0, OP_ENQ, ST_OK, 1, 0, 1), (1, OP_ENQ, ST_FULL, 2, 2, 3)]
