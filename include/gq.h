@@ -69,7 +69,7 @@ typedef enum { GQ_SLOTS_REMAP = 0, GQ_SLOTS_PADDED = 1, GQ_SLOTS_LINEAR = 2 } gq
  *                      payload atomically and waits for it before the install,
  *                      which needs no cache write-back or invalidate);
  *   GQ_OPT_WFQ_TUNING  use wfq_patience_enq / wfq_patience_deq / wfq_help_delay
- *                      instead of the defaults (16 / 64 / 64); a patience of 0
+ *                      instead of the defaults (64 / 256 / 64); a patience of 0
  *                      sends every G-WFQ operation down the slow path.          */
 #define GQ_OPT_FENCED 1u
 #define GQ_OPT_WFQ_TUNING 2u

@@ -56,7 +56,7 @@ class _Options(ctypes.Structure):
 def make_options(slot_mode="linear", fenced=False, ymc_pool_cells=0, patience=None,
                  help_delay=None, ticket_group=0) -> _Options:
     flags = GQ_OPT_FENCED if fenced else 0
-    pe, pd, hd = 16, 64, 64
+    pe, pd, hd = 64, 256, 64
     if patience is not None or help_delay is not None:
         flags |= GQ_OPT_WFQ_TUNING
         if patience is not None:

@@ -837,8 +837,8 @@ static gq_dev make_dev(gq_kind kind, uint64_t capacity, uint32_t item_width,
   d.flags = o.flags;
   d.capacity = capacity;
   d.group_lanes = o.ticket_group ? o.ticket_group : kDefaultGroupLanes;
-  d.patience_enq = 16;
-  d.patience_deq = 64;
+  d.patience_enq = 64;
+  d.patience_deq = 256;
   d.help_delay = 64;
   if (o.flags & GQ_OPT_WFQ_TUNING) {
     d.patience_enq = o.wfq_patience_enq;

@@ -72,13 +72,6 @@ def test_c3_full_size_conservation(kind, prod_waves, log2_inv_p):
     if kind == "ymc" and prod_waves == 128:
         pytest.skip("G-WFQ-YMC takes a cell per empty poll: 57,344 polling consumers exhaust "
                     "even 2^30 cells (its memory is not bounded, Section III-A)")
-    if kind == "wfq" and (prod_waves == 128 or (prod_waves == 896 and log2_inv_p == 6)):
-        pytest.skip("G-WFQ with 57,344 polling consumers, or 57,344 producers retrying on "
-                    "FULL with one lane in 64 active per round: slow-path requests outlast "
-                    "the 10 s fail-safe bound now and then (each such request ends with "
-                    "GQ_ERR_DEVICE and drops its operation); measured 8,388,055 of 8,388,608 "
-                    "items at 128 producer wavefronts, p = 1/2, and 1.5-1.8 M at p = 1/64 "
-                    "in 20 s")
     T = torch()
     seed = workloads.run_seed(3, prod_waves + log2_inv_p)
     q, role, quota, target, c, _ = c3_run(kind, 1 << 16, 1024, prod_waves, log2_inv_p,
