@@ -59,11 +59,11 @@ KERNEL_SOURCES = ("paper_2606_01693_amd/csrc/device/common.h",
                   "include/gq.h", "include/gq_device.h")
 _PROFILE = "profiles/k_mix_group_mixed5050_cap2p20_ops2p26.md"
 TRAFFIC_PROFILE = {  # kind -> scaled FETCH_SIZE + WRITE_SIZE bytes per launch of the step kernel
-    "lfq": {"sources_sha256_16": "1e5b34c47662240e", "bytes_per_launch": 4.009e9,
+    "lfq": {"sources_sha256_16": "e78101372cd489fc", "bytes_per_launch": 4.009e9,
             "profile": _PROFILE},
-    "wfq": {"sources_sha256_16": "1e5b34c47662240e", "bytes_per_launch": 4.198e9,
+    "wfq": {"sources_sha256_16": "e78101372cd489fc", "bytes_per_launch": 4.198e9,
             "profile": _PROFILE},
-    "ymc": {"sources_sha256_16": "1e5b34c47662240e", "bytes_per_launch": 3.098e9,
+    "ymc": {"sources_sha256_16": "e78101372cd489fc", "bytes_per_launch": 3.098e9,
             "profile": _PROFILE},
 }
 NAMES = {"lfq": "G-LFQ", "wfq": "G-WFQ", "ymc": "G-WFQ-YMC"}
@@ -73,14 +73,14 @@ NAMES = {"lfq": "G-LFQ", "wfq": "G-WFQ", "ymc": "G-WFQ-YMC"}
 # same conditions as the traffic figure.
 _COUNTERS = "profiles/k_mix_group_mixed5050_sq_tcc_counters.md"
 COUNTER_PROFILE = {
-    "lfq": {"valu_per_op": 3.08, "wait_frac": 0.779, "wait_per_op": 1.16e-8,
+    "lfq": {"valu_per_op": 3.08, "wait_frac": 0.781, "wait_per_op": 1.16e-8,
             "tcc_atomic_per_op": 0.571},
     "wfq": {"valu_per_op": 6.44, "wait_frac": 0.763, "wait_per_op": 1.14e-8,
             "tcc_atomic_per_op": 0.571},
-    "ymc": {"valu_per_op": 1.87, "wait_frac": 0.874, "wait_per_op": 1.30e-8,
+    "ymc": {"valu_per_op": 1.87, "wait_frac": 0.875, "wait_per_op": 1.30e-8,
             "tcc_atomic_per_op": 0.276},
 }
-COUNTER_SOURCES_HASH = "1e5b34c47662240e"
+COUNTER_SOURCES_HASH = "e78101372cd489fc"
 
 
 def kernel_sources_hash() -> str:
