@@ -847,6 +847,13 @@ def main():
         log(f"[bench] multi: {out['batched_multi_queue']}")
     if not args.no_c3:
         out["imbalanced_prodcons"] = bench_c3(gq, torch)
+        from paper_2606_01693_amd import autotune
+        t = autotune.tune_prodcons("wfq", prod_waves=128, log2_inv_p=1,
+                                   patience_options=((16, 64), (64, 256), (256, 1024)),
+                                   help_delays=(64,), time_limit_ms=5000)
+        out["imbalanced_prodcons"]["wfq_patience_tuning_128_896_p_half"] = {
+            "best": t.best, "best_ms": t.best_ms, "table": t.table}
+        log(f"[bench] c3 G-WFQ patience tuning 128:896 p=1/2: best {t.best} {t.best_ms:.1f} ms")
     if not args.no_bfs:
         out["bfs"] = bench_bfs(gq, torch)
     if not args.no_serve:

@@ -12,6 +12,11 @@ Two searches, each timing real launches on the current device with HIP events
   the 50/50 mix, the many-queue configuration), so more lanes means fewer
   operations per lane.
 
+* ``tune_prodcons`` -- G-WFQ's slow-path knobs under an imbalanced
+  producer/consumer run (the C3 shape): patience (enqueue, dequeue) and help
+  delay D.  A run counts only when every item went through with the
+  multiset checksums equal; the fastest such configuration wins.
+
 Results are cached in a JSON file keyed by device architecture, queue kind
 and sizes; a cached key is returned without measuring unless ``force``.  The
 measuring function can be replaced (``measure=``), which is how the search
@@ -213,5 +218,67 @@ def _multi_measure(kind, caps, ops_factor, reps):
                 m.close()
             for q in qs:
                 q.close()
+
+    return run
+
+
+def tune_prodcons(kind: str = "wfq", capacity: int = 1 << 16, waves: int = 1024,
+                  prod_waves: int = 128, log2_inv_p: int = 0, items: int = 1 << 23,
+                  patience_options=((16, 64), (64, 256), (256, 1024)),
+                  help_delays=(16, 64, 256), time_limit_ms: int = 20000,
+                  cache_path: str = "", force: bool = False,
+                  measure: Callable[[Dict], tuple] = None) -> TuneResult:
+    """Fastest (patience, help delay) for one imbalanced producer/consumer
+    configuration: `waves` wavefronts of which the seed makes `prod_waves`
+    producers, activity probability 2^-log2_inv_p, `items` items.  The
+    measure returns (ms, successful operations); a run that does not finish
+    or breaks conservation raises and is recorded as failed."""
+    key = (f"prodcons/{_arch_or('any', measure)}/{kind}/cap{capacity}/w{waves}/p{prod_waves}"
+           f"/a{log2_inv_p}/i{items}")
+    cands = [dict(patience=list(pt), help_delay=d)
+             for pt, d in itertools.product(patience_options, help_delays)]
+    if measure is None:
+        measure = _prodcons_measure(kind, capacity, waves, prod_waves, log2_inv_p, items,
+                                    time_limit_ms)
+    return _search(key, cands, measure, cache_path, force)
+
+
+def _prodcons_measure(kind, capacity, waves, prod_waves, log2_inv_p, items, time_limit_ms):
+    import torch
+
+    import workloads
+
+    from . import GQ_OK, Queue
+
+    lanes = waves * 64
+
+    def run(c):
+        q = Queue(kind, capacity, item_width=8, max_threads=lanes,
+                  patience=tuple(c["patience"]), help_delay=c["help_delay"])
+        try:
+            seed = workloads.run_seed(3, prod_waves + log2_inv_p)
+            mask = workloads.producer_waves(seed, waves, prod_waves)
+            role = torch.tensor(np.repeat(np.where(mask, 0, 1), 64).astype(np.uint8),
+                                device="cuda")
+            quota = -(-items // (prod_waves * 64))
+            target = quota * prod_waves * 64
+            counts = torch.zeros(8, dtype=torch.int64, device="cuda")
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            q.run_prodcons(seed, lanes, 256, role, quota, target, log2_inv_p, 0, counts,
+                           max_rounds=1 << 30, time_limit_ms=time_limit_ms)
+            e1.record()
+            torch.cuda.synchronize()
+            c8 = counts.cpu().numpy().view(np.uint64)
+            err = q.check_error()
+            if err != GQ_OK or c8[0] != target or c8[1] != target or c8[4] != c8[6] \
+                    or c8[5] != c8[7]:
+                raise RuntimeError(f"run did not complete: error {err}, "
+                                   f"{int(c8[0])}/{int(c8[1])} of {target}")
+            return e0.elapsed_time(e1), 2 * target
+        finally:
+            q.close()
 
     return run

@@ -84,3 +84,21 @@ def test_tune_multi_with_fake_measure(tmp_path):
 
     r = at.tune_multi("lfq", [256, 512, 1024], cache_path=str(tmp_path / "c.json"), measure=meas)
     assert r.best == {"waves_per_256_slots": 1}
+
+
+def test_tune_prodcons_keeps_only_completed_runs(tmp_path):
+    """Runs that time out or break conservation raise inside the measure and
+    are recorded as failed; the fastest completed one wins."""
+    from paper_2606_01693_amd import autotune as at
+
+    def fake(c):
+        pe, pd = c["patience"]
+        if pe == 16:
+            raise RuntimeError("run did not complete")
+        return 100.0 / pe + c["help_delay"] / 1000.0, 1 << 24
+
+    path = str(tmp_path / "pc.json")
+    r = at.tune_prodcons(cache_path=path, measure=fake)
+    assert r.best == {"patience": [256, 1024], "help_delay": 16}
+    assert sum("error" in t for t in r.table) == 3 and len(r.table) == 9
+    assert at.cached(path, r.key).best == r.best

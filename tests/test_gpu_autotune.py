@@ -22,3 +22,15 @@ def test_tune_multi_small():
     r = at.tune_multi("lfq", caps, waves_per_256_slots=(0.5, 1, 2), reps=2)
     assert r.best["waves_per_256_slots"] in (0.5, 1, 2)
     assert all("mops" in t for t in r.table)
+
+
+def test_tune_prodcons_small():
+    """A 64-wavefront 8:56 polling run: every measured configuration either
+    completes with conservation or is recorded as failed, and the best is a
+    completed one."""
+    from paper_2606_01693_amd import autotune as at
+    r = at.tune_prodcons("wfq", capacity=1 << 10, waves=64, prod_waves=8, log2_inv_p=0,
+                         items=1 << 16, patience_options=((16, 64), (64, 256)),
+                         help_delays=(64,), time_limit_ms=10000)
+    good = [t for t in r.table if "mops" in t]
+    assert good and r.best_mops == max(t["mops"] for t in good)
