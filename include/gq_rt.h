@@ -83,7 +83,10 @@ gq_status gq_rt_create(gq_kind kind, uint32_t width, uint32_t height, uint32_t t
 gq_status gq_rt_render(gq_rt *rt, const gq_rt_scene *scene, uint32_t method, float *d_image,
                        uint32_t *d_segments, uint64_t *d_stats, void *stream);
 
-/* Latched device error of the last render (GQ_OK if none); synchronizes `stream`. */
+/* Latched device error of the last render (GQ_OK if none); synchronizes `stream`.
+ * A queue render that ended with a path still unfinished also reports
+ * GQ_ERR_DEVICE; after any error the next queue render resets the tile queues
+ * first. */
 gq_status gq_rt_check_error(gq_rt *rt, void *stream);
 
 gq_status gq_rt_destroy(gq_rt *rt);
