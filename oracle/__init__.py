@@ -162,6 +162,27 @@ def conservation(put_in, taken_out):
     return {"lost": int(out[0]), "extra": int(out[1]), "dup_in": int(out[2])}
 
 
+def multiset_checksums(values):
+    """(count, S1, S2) of a multiset of 64-bit items: S1 and S2 are the sums of
+    v and of v * v taken modulo 2^64 (wrapping arithmetic).  Equal multisets
+    have equal checksums; the device drivers report the same three numbers
+    for the items they moved, so conservation (Section IV, each token exactly
+    once) can be checked where no per-operation history is recorded."""
+    v = _u64(values)
+    with np.errstate(over="ignore"):
+        return int(v.shape[0]), int(v.sum(dtype=np.uint64)), int((v * v).sum(dtype=np.uint64))
+
+
+def mix_tokens_from_counts(lane_enq, lane0: int = 0):
+    """The tokens a run's lanes enqueued successfully, given each lane's count
+    of successful enqueues: lane g's j-th one carries (g << 32) | (j + 1)
+    (the Section IV token format)."""
+    cnt = np.asarray(lane_enq, dtype=np.int64)
+    lanes = np.repeat(np.arange(lane0, lane0 + cnt.shape[0], dtype=np.uint64), cnt)
+    within = np.arange(int(cnt.sum()), dtype=np.int64) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+    return (lanes << np.uint64(32)) | (within + 1).astype(np.uint64)
+
+
 # ----------------------------------------------------------------------------
 # O4 per-producer order
 # ----------------------------------------------------------------------------

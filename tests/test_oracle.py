@@ -586,3 +586,37 @@ def test_locked_queue_multithread_balance():
     oke, okd, sec = oracle.locked_queue_run(roles, 128, 64)
     assert 0 <= 64 + oke - okd <= 128
     assert sec > 0
+
+
+# ---------------------------------------------------------------------------
+# Multiset checksums (the conservation check of runs without a history)
+# ---------------------------------------------------------------------------
+def test_multiset_checksums_against_big_integers():
+    rng = np.random.default_rng(17)
+    v = rng.integers(0, 2**63, size=5000, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+    n, s1, s2 = oracle.multiset_checksums(v)
+    ints = [int(x) for x in v]
+    assert n == 5000
+    assert s1 == sum(ints) % 2**64
+    assert s2 == sum(x * x for x in ints) % 2**64
+
+
+def test_multiset_checksums_closed_form_and_order_free():
+    # 1..m: sum m(m+1)/2, sum of squares m(m+1)(2m+1)/6 (no wrap at this size)
+    m = 100000
+    v = np.arange(1, m + 1, dtype=np.uint64)
+    assert oracle.multiset_checksums(v) == (m, m * (m + 1) // 2, m * (m + 1) * (2 * m + 1) // 6)
+    rng = np.random.default_rng(3)
+    assert oracle.multiset_checksums(rng.permutation(v)) == oracle.multiset_checksums(v)
+    # a duplicate in place of another item changes S1 (here) or S2
+    w = v.copy()
+    w[10] = w[11]
+    assert oracle.multiset_checksums(w) != oracle.multiset_checksums(v)
+    assert oracle.multiset_checksums([]) == (0, 0, 0)
+
+
+def test_mix_tokens_from_counts():
+    toks = oracle.mix_tokens_from_counts([2, 0, 3], lane0=5)
+    want = [(5 << 32) | 1, (5 << 32) | 2, (7 << 32) | 1, (7 << 32) | 2, (7 << 32) | 3]
+    assert toks.tolist() == want
+    assert oracle.mix_tokens_from_counts([]).size == 0
