@@ -212,7 +212,10 @@ def violation_scan(h: History, prefill=(), drain=(), capacity: int = 0):
                                   capacity, _p(out))
     if rc < 0:
         raise MemoryError("orc_violation_scan")
-    return {k: int(v) for k, v in zip(VIOLATIONS, out)}
+    rep = {k: int(v) for k, v in zip(VIOLATIONS, out)}
+    if rc != int(any(rep.values())):
+        raise AssertionError(f"orc_violation_scan returned {rc} with counts {rep}")
+    return rep
 
 
 def all_zero(d: dict) -> bool:

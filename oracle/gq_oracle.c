@@ -509,7 +509,7 @@ int orc_violation_scan(uint64_t m, const uint8_t *op, const uint8_t *st,
 #undef T_OF
     free(E); free(D); free(by_ee); free(qs);
     free(enq_end); free(enq_call); free(deq_end); free(deq_call);
-    for (int c = 0; c < 7; c++)
+    for (int c = 0; c < 8; c++)
         if (counts[c]) return 1;
     return 0;
 }

@@ -365,6 +365,29 @@ def test_scan_union_witness():
     assert scan(rows, drain=[1])["witness_union"] == 1
 
 
+def test_scan_return_code_covers_every_pattern():
+    """The C entry point returns 1 exactly when some count is nonzero, the
+    union witness (the last count) included: the history above that only the
+    union witness flags must make it return 1."""
+    rows = [(0, OP_ENQ, ST_OK, 1, 0, 1), (1, OP_ENQ, ST_OK, 2, 2, 5),
+            (2, OP_DEQ, ST_EMPTY, 0, 4, 10), (3, OP_DEQ, ST_OK, 1, 7, 8),
+            (4, OP_DEQ, ST_OK, 2, 12, 13)]
+    h = oracle.History.from_rows(rows)
+    L = oracle.lib()
+    out = np.zeros(len(oracle.VIOLATIONS), dtype=np.uint64)
+    z = np.zeros(0, dtype=np.uint64)
+    rc = L.orc_violation_scan(len(h), oracle._p(h.op), oracle._p(h.st), oracle._p(h.val),
+                              oracle._p(h.call), oracle._p(h.ret), 0, oracle._p(z), 0,
+                              oracle._p(z), 0, oracle._p(out))
+    assert rc == 1 and int(out[-1]) == 1 and int(out[:-1].sum()) == 0
+    legal = [(0, OP_ENQ, ST_OK, 1, 0, 1), (1, OP_DEQ, ST_OK, 1, 2, 3)]
+    h = oracle.History.from_rows(legal)
+    rc = L.orc_violation_scan(len(h), oracle._p(h.op), oracle._p(h.st), oracle._p(h.val),
+                              oracle._p(h.call), oracle._p(h.ret), 0, oracle._p(z), 0,
+                              oracle._p(z), 0, oracle._p(out))
+    assert rc == 0 and int(out.sum()) == 0
+
+
 def test_scan_spurious_full():
     # capacity 2: one item in the queue, FULL answered: impossible
     rows = [(0, OP_ENQ, ST_OK, 1, 0, 1), (1, OP_ENQ, ST_FULL, 2, 2, 3)]
