@@ -51,10 +51,10 @@ HBM_PEAK_GBS = 8000.0
 # Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of the timed kernel, from the
 # two rocprofv3 --pmc runs summarised in the named profile; reported only while
 # the kernel sources hash to the value they had when the counters were taken.
-KERNEL_SOURCES = ("paper_2606_01693_amd/csrc/device/common.h",
-                  "paper_2606_01693_amd/csrc/device/lfq.h",
-                  "paper_2606_01693_amd/csrc/device/wfq.h",
-                  "paper_2606_01693_amd/csrc/device/ymc.h",
+KERNEL_SOURCES = ("include/gq/common.h",
+                  "include/gq/lfq.h",
+                  "include/gq/wfq.h",
+                  "include/gq/ymc.h",
                   "paper_2606_01693_amd/csrc/gq_lib.hip",
                   "include/gq.h", "include/gq_device.h")
 _PROFILE = "profiles/k_mix_group_mixed5050_cap2p20_ops2p26.md"

@@ -5,7 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../../include/gq.h"
+#include "../gq.h"
 
 namespace gq {
 

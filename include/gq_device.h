@@ -33,9 +33,9 @@
 #define GQ_DEVICE_H
 
 #include "gq.h"
-#include "../paper_2606_01693_amd/csrc/device/lfq.h"
-#include "../paper_2606_01693_amd/csrc/device/wfq.h"
-#include "../paper_2606_01693_amd/csrc/device/ymc.h"
+#include "gq/lfq.h"
+#include "gq/wfq.h"
+#include "gq/ymc.h"
 
 template <int KIND>
 __device__ __forceinline__ int gq_enqueue_k(const gq_dev& q, uint64_t item, uint32_t tid,
