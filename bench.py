@@ -276,7 +276,7 @@ def bench_multi(gq, torch, kind="lfq", nq=256, ops=16, reps=5):
         q.enqueue_batch(t)
         pre_items.append(t)
     m = gq.Multi(qs, lanes, block=256)
-    counts = torch.zeros(4 * nq, dtype=torch.int64, device="cuda")
+    counts = torch.zeros(8 * nq, dtype=torch.int64, device="cuda")
     s = torch.cuda.Stream()
     total_ops = sum(lanes) * ops
     res = {"queues": nq, "capacities_log2_range": [8, 16], "total_lanes": sum(lanes),
@@ -285,7 +285,7 @@ def bench_multi(gq, torch, kind="lfq", nq=256, ops=16, reps=5):
     torch.cuda.synchronize()  # prefill ran on the default stream
 
     def ok_count():
-        c = counts.cpu().numpy().reshape(-1, 4)
+        c = counts.cpu().numpy().reshape(-1, 8)
         return int(c[:, 0].sum() + c[:, 1].sum())
 
     with torch.cuda.stream(s):
@@ -321,7 +321,7 @@ def bench_multi(gq, torch, kind="lfq", nq=256, ops=16, reps=5):
         e0.record(s)
         for r in range(reps):
             for i, q in enumerate(qs):
-                q.run_mix(seed + 1000 + r, lanes[i], ops, counts[4 * i:4 * i + 4], stream=s)
+                q.run_mix(seed + 1000 + r, lanes[i], ops, counts[8 * i:8 * i + 8], stream=s)
         e1.record(s)
         s.synchronize()
         ms = e0.elapsed_time(e1) / reps
@@ -357,7 +357,7 @@ def bench_ticket_ablation(gq, torch, kinds, seed, args, reps=3):
                          ymc_pool_cells=(1 << 28) if kind == "ymc" else 0, ticket_group=tg)
             pre = torch.arange(1, CAP // 2 + 1, dtype=torch.int64, device="cuda") | (0xFFFFFFFF << 32)
             q.enqueue_batch(pre)
-            counts = torch.zeros(4, dtype=torch.int64, device="cuda")
+            counts = torch.zeros(8, dtype=torch.int64, device="cuda")
             ms = []
             for r in range(reps + 1):
                 e0, e1 = _events(torch)
@@ -371,8 +371,10 @@ def bench_ticket_ablation(gq, torch, kinds, seed, args, reps=3):
             ok = (c[0] + c[1]) / (reps + 1)
             med = float(np.median(ms))
             assert q.check_error() == gq.GQ_OK
-            out[f"{NAMES[kind]} group={tg}"] = {"kernel_ms": med,
-                                                "mops": ok / (med * 1e-3) / 1e6}
+            out[f"{NAMES[kind]} group={tg}"] = {
+                "kernel_ms": med, "mops": ok / (med * 1e-3) / 1e6,
+                "launch": (f"{LANES // 256} WGs x 256 lanes, per-wavefront tickets" if tg == 64
+                           else f"{LANES // tg} WGs x {tg} lanes, one ticket FAA per WG")}
             log(f"[bench] tickets {NAMES[kind]} group={tg}: {med:.2f} ms, "
                 f"{ok / (med * 1e-3) / 1e6:.0f} Mops/s")
             q.close()
@@ -508,23 +510,28 @@ def bench_serve(gq, torch, njobs=1000, pool_size=64, team_lanes=1024, budget=16 
 
 def bench_c2(gq, torch, kinds, seed, args):
     """The throughput sweep's other points: (a) the mixed 50/50 workload with
-    2^26 attempts split over G = 1, 2, 4, ..., 2048 workgroups of 256 lanes;
-    (b) 32 fill/drain rounds through the host batch API (enqueue a batch of
-    n = 2^20 items, then dequeue a batch of n).  Kernel time by events."""
+    2^26 attempts split over G x 256 lanes, G = 1, 2, 4, ..., 2048 (the lanes
+    run in workgroups of min(ticket group, G x 256) lanes -- 1024 by default --
+    each taking its first tickets with one FAA per counter; the queue is reset
+    and prefilled to n/2 before each point); (b) 32 fill/drain rounds through
+    the host batch API (enqueue a batch of n = 2^20 items, then dequeue a batch
+    of n).  Kernel time by events."""
     out = {"mix_by_workgroups": {}, "fill_drain": {}}
     total = 1 << 26
+    group = args.ticket_group or 1024
     for kind in kinds:
         q = gq.Queue(kind, CAP, item_width=ITEM_BYTES, max_threads=LANES,
-                     ymc_pool_cells=(1 << 29) if kind == "ymc" else 0,
+                     ymc_pool_cells=(1 << 27) if kind == "ymc" else 0,
                      ticket_group=args.ticket_group)
         pre = torch.arange(1, CAP // 2 + 1, dtype=torch.int64, device="cuda") | (0xFFFFFFFF << 32)
-        q.enqueue_batch(pre)
-        counts = torch.zeros(4, dtype=torch.int64, device="cuda")
+        counts = torch.zeros(8, dtype=torch.int64, device="cuda")
         row = {}
         g = 1
         while g <= 2048:
             lanes = g * 256
             ops = total // lanes
+            q.reset()
+            q.enqueue_batch(pre)
             counts.zero_()
             e0, e1 = _events(torch)
             e0.record()
@@ -533,7 +540,9 @@ def bench_c2(gq, torch, kinds, seed, args):
             torch.cuda.synchronize()
             c = counts.cpu().tolist()
             ms = e0.elapsed_time(e1)
-            row[str(g)] = {"ms": ms, "mops": (c[0] + c[1]) / (ms * 1e-3) / 1e6}
+            wg = min(group, lanes) if group > 64 else 256
+            row[f"{g}x256"] = {"ms": ms, "mops": (c[0] + c[1]) / (ms * 1e-3) / 1e6,
+                               "launch": f"{lanes // wg} WGs x {wg} lanes"}
             g *= 2
         assert q.check_error() == gq.GQ_OK
         out["mix_by_workgroups"][NAMES[kind]] = row
@@ -660,6 +669,134 @@ def bench_c3(gq, torch, kinds=("lfq", "wfq", "ymc"), items=1 << 23, cap=1 << 16,
     return out
 
 
+# The step's headline queue: G-WFQ, the paper's wait-free queue (its first
+# contribution).  G-LFQ and G-WFQ-YMC run the same step and are reported under
+# "variants".
+HEADLINE = "wfq"
+# G-WFQ-YMC's cell pool: the queue is reset and prefilled before every step
+# (outside the timed region), so the pool needs to hold one step's cells only:
+# every attempt takes at most one T or H ticket on the fast path (a ticket is a
+# cell), i.e. LANES * OPS_PER_LANE cells, plus the prefill's n/2, plus slow-path
+# retries, far below 2^27 cells (3 GiB).
+YMC_STEP_POOL = 1 << 27
+
+
+def step_plan(steps: int, warmup: int) -> dict:
+    """How the timed steps use the queues: every step starts from a freshly
+    reset queue prefilled to n/2, so nothing a step needs grows with the
+    number of steps (G-WFQ-YMC's pool in particular)."""
+    need = LANES * OPS_PER_LANE + CAP // 2
+    return {"launches": warmup + steps, "reset_each_step": True,
+            "ymc_pool_cells": YMC_STEP_POOL, "ymc_cells_needed_per_step": need,
+            "fits": need <= YMC_STEP_POOL}
+
+
+def launch_desc(ticket_group: int) -> str:
+    g = ticket_group or 1024
+    if g <= 64:
+        return f"{LANES // 256} WGs x 256 lanes, per-wavefront ticket FAAs"
+    return f"{LANES // g} WGs x {g} lanes, one ticket FAA per counter per WG"
+
+
+def checksums(v: np.ndarray):
+    """(count, wrapping sum of v, wrapping sum of v*v) of uint64 items."""
+    with np.errstate(over="ignore"):
+        return (int(v.shape[0]), int(v.sum(dtype=np.uint64)), int((v * v).sum(dtype=np.uint64)))
+
+
+def csum_add(a, b):
+    m = (1 << 64) - 1
+    return a[0] + b[0], (a[1] + b[1]) & m, (a[2] + b[2]) & m
+
+
+def run_variant(gq, torch, kind, args, base_seed):
+    """Warmup + timed steps of one queue variant.  Each step: reset the queue
+    and prefill it to n/2 (untimed), synchronise, launch the mixed kernel
+    (timed by wall clock with a synchronisation on both sides, and by HIP
+    events on the launch stream), then drain what is left (untimed) and check
+    conservation of the step with the kernel's multiset checksums: prefill +
+    enqueued = dequeued + drained (counts and wrapping sums of v and v*v)."""
+    q = gq.Queue(kind, CAP, item_width=ITEM_BYTES, max_threads=LANES,
+                 slot_mode=args.slot_mode, fenced=args.fenced,
+                 ymc_pool_cells=YMC_STEP_POOL if kind == "ymc" else 0,
+                 ticket_group=args.ticket_group)
+    try:
+        pre = torch.arange(1, CAP // 2 + 1, dtype=torch.int64, device="cuda") | (0xFFFFFFFF << 32)
+        pre_sums = checksums(pre.cpu().numpy().view(np.uint64))
+        counts = torch.zeros(8, dtype=torch.int64, device="cuda")
+        out = torch.zeros(CAP, dtype=torch.int64, device="cuda")
+        ost = torch.zeros(CAP, dtype=torch.uint8, device="cuda")
+        kms, walls, oks, conserved = [], [], [], True
+        q.clear_stats()
+        for i in range(args.warmup + args.steps):
+            q.reset()
+            q.enqueue_batch(pre)
+            counts.zero_()
+            torch.cuda.synchronize()
+            e0, e1 = _events(torch)
+            t0 = time.perf_counter()
+            e0.record()
+            q.run_mix(base_seed + i, LANES, OPS_PER_LANE, counts)
+            e1.record()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            # untimed: drain the remainder and check the step's conservation
+            q.dequeue_batch(out, ost)
+            c = counts.cpu().numpy().view(np.uint64).tolist()
+            st = ost.cpu().numpy()
+            left = out.cpu().numpy().view(np.uint64)[st == gq.GQ_OK]
+            put = csum_add(pre_sums, (c[0], c[6], c[7]))
+            got = csum_add((c[1], c[4], c[5]), checksums(left))
+            ok_step = put == got and c[0] + c[1] + c[2] + c[3] == LANES * OPS_PER_LANE
+            conserved &= ok_step
+            if i >= args.warmup:
+                kms.append(e0.elapsed_time(e1))
+                walls.append((t1 - t0) * 1e3)
+                oks.append(c[0] + c[1])
+        err = q.check_error()
+        st = q.stats()
+        kms_a, walls_a = np.array(kms), np.array(walls)
+        ok_mean = float(np.mean(oks))
+        res = {
+            "name": NAMES[kind],
+            "kernel": (f"k_mix<{NAMES[kind]}>" if (args.ticket_group or 1024) <= 64
+                       else f"k_mix_group<{NAMES[kind]}>"),
+            "launch": launch_desc(args.ticket_group),
+            "mops": sum(oks) / (walls_a.sum() * 1e-3) / 1e6,
+            "mops_kernel": ok_mean / (float(np.median(kms_a)) * 1e-3) / 1e6,
+            "ok_ops_per_step": ok_mean,
+            "kernel_ms": {"median": float(np.median(kms_a)), "mean": float(kms_a.mean()),
+                          "min": float(kms_a.min()), "max": float(kms_a.max()),
+                          "per_step": [round(x, 4) for x in kms]},
+            "step_wall_ms": {"median": float(np.median(walls_a)), "mean": float(walls_a.mean()),
+                             "min": float(walls_a.min()), "max": float(walls_a.max())},
+            "conserved_every_step": bool(conserved),
+            "device_error": gq.status_str(err) if err else None,
+            "dropped_ops": st.dropped,
+            "cas_fail_per_ok_op": st.cas_fail / max(1, sum(oks)),
+            "slow_path_entries_per_step": st.slow_enter / (args.warmup + args.steps),
+            "helps_per_step": st.helps / (args.warmup + args.steps),
+        }
+        log(f"[bench] {kind}: kernel ms median {res['kernel_ms']['median']:.3f} "
+            f"(min {res['kernel_ms']['min']:.3f}, max {res['kernel_ms']['max']:.3f}), "
+            f"{res['mops']:.0f} Mops/s by wall clock, conserved={conserved}, err={err}")
+        return res
+    finally:
+        q.close()
+
+
+def section(out, key, fn):
+    """Run one bench section; an exception is recorded, not fatal."""
+    t0 = time.perf_counter()
+    try:
+        out[key] = fn()
+    except Exception as e:  # noqa: BLE001 -- the JSON line must still be printed
+        out[key] = {"error": f"{type(e).__name__}: {e}"}
+        log(f"[bench] section {key} failed: {e}")
+    out.setdefault("section_seconds", {})[key] = round(time.perf_counter() - t0, 1)
+    log(f"[bench] section {key}: {out['section_seconds'][key]} s")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -696,101 +833,50 @@ def main():
     info = gq.device_info()
     log(f"[bench] device {info}")
     kinds = [k for k in args.kinds.split(",") if k]
+    head = HEADLINE if HEADLINE in kinds else kinds[0]
     base_seed = workloads.run_seed(2, 0)
-    queues, counts = {}, {}
-    for kind in kinds:
-        # G-WFQ-YMC's pool must cover every ticket of the run (no reset
-        # between steps): 2^29 cells of 24 B (12 GiB).
-        q = gq.Queue(kind, CAP, item_width=ITEM_BYTES, max_threads=LANES,
-                     slot_mode=args.slot_mode, fenced=args.fenced,
-                     ymc_pool_cells=(1 << 29) if kind == "ymc" else 0,
-                     ticket_group=args.ticket_group)
-        pre = torch.arange(1, CAP // 2 + 1, dtype=torch.int64, device="cuda") | (0xFFFFFFFF << 32)
-        q.enqueue_batch(pre)
-        queues[kind] = q
-        counts[kind] = torch.zeros(4, dtype=torch.int64, device="cuda")
-    step = 0
-    for _ in range(args.warmup):
-        for kind in kinds:
-            queues[kind].run_mix(base_seed + step, LANES, OPS_PER_LANE, counts[kind])
-        step += 1
-    torch.cuda.synchronize()
-    for kind in kinds:
-        assert queues[kind].check_error() == gq.GQ_OK, kind
-        counts[kind].zero_()
-        queues[kind].clear_stats()
-    events = {k: [] for k in kinds}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        for kind in kinds:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            queues[kind].run_mix(base_seed + step, LANES, OPS_PER_LANE, counts[kind])
-            e1.record()
-            events[kind].append((e0, e1))
-        step += 1
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
+    plan = step_plan(args.steps, args.warmup)
     variants = {}
-    ok_total = 0
     for kind in kinds:
-        err = queues[kind].check_error()
-        if err != gq.GQ_OK:
-            raise SystemExit(f"device error on {kind}: {gq.status_str(err)}")
-        c = counts[kind].cpu().tolist()
-        ok = c[0] + c[1]
-        ok_total += ok
-        kms = [a.elapsed_time(b) for a, b in events[kind]]
-        kavg = float(np.mean(kms))
-        per_launch_ok = ok / args.steps
-        st = queues[kind].stats()
-        variants[kind] = {
-            "name": NAMES[kind],
-            "mops": per_launch_ok / (kavg * 1e-3) / 1e6,
-            "kernel_ms_avg": kavg,
-            "ok_ops_per_step": per_launch_ok,
-            "full_per_step": c[2] / args.steps,
-            "empty_per_step": c[3] / args.steps,
-            "cas_fail_per_ok_op": st.cas_fail / max(1, ok),
-            "slow_path_entries_per_step": st.slow_enter / args.steps,
-            "helps_per_step": st.helps / args.steps,
-        }
-        log(f"[bench] {kind}: counts {c} kernel_ms={kms}")
-    value = ok_total / wall / 1e6
-    dom = max(kinds, key=lambda k: variants[k]["kernel_ms_avg"])
-    dv = variants[dom]
-    bpo = BYTES_PER_OP_KIND[dom]
-    achieved_gbs = dv["ok_ops_per_step"] * bpo / (dv["kernel_ms_avg"] * 1e-3) / 1e9
-    traffic = TRAFFIC_PROFILE.get(dom)
+        try:
+            variants[kind] = run_variant(gq, torch, kind, args, base_seed)
+        except Exception as e:  # noqa: BLE001 -- report and go on with the other variants
+            variants[kind] = {"name": NAMES[kind], "error": f"{type(e).__name__}: {e}"}
+            log(f"[bench] {kind} failed: {e}")
+        torch.cuda.empty_cache()
+    hv = variants[head]
+    ok_head = "error" not in hv and hv["conserved_every_step"] and hv["device_error"] is None
     out = {
         "metric": "Mops/s enq+deq at 50/50 mix, 2^20-slot queue",
-        "value": value,
+        "value": hv["mops"] if ok_head else None,
         "unit": "Mops/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": hv["step_wall_ms"]["mean"] if "error" not in hv else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
         "config": {
-            "workload": "mixed 50/50 enqueue/dequeue, capacity 2^20, uint64 payload, 2^26 op "
-                        "attempts per queue per step by 2048 WGs x 256 lanes, prefill n/2; one "
-                        "step runs that batch through each queue variant in turn: "
-                        + ", ".join(NAMES[k] for k in kinds)
-                        + f"; slots={args.slot_mode}, hand-off="
-                        + ("fenced" if args.fenced else "atomic")
-                        + f", first tickets per {args.ticket_group or 1024} lanes",
-            "capacity": CAP, "lanes": LANES, "ops_per_lane": OPS_PER_LANE,
-            "variants": kinds, "parallelism": "single GPU",
+            "workload": f"{NAMES[head]}: mixed 50/50 enqueue/dequeue, capacity 2^20, uint64 "
+                        f"payload, 2^26 op attempts per step by 2^19 lanes x 128 ops "
+                        f"({launch_desc(args.ticket_group)}), queue reset and prefilled to n/2 "
+                        f"before each step (untimed); slots={args.slot_mode}, hand-off="
+                        + ("fenced" if args.fenced else "atomic"),
+            "queue": NAMES[head], "capacity": CAP, "lanes": LANES, "ops_per_lane": OPS_PER_LANE,
+            "parallelism": "single GPU",
         },
+        "step_plan": plan,
         "variants": variants,
-        "roofline": {
+    }
+    if "error" not in hv:
+        bpo = BYTES_PER_OP_KIND[head]
+        kavg = hv["kernel_ms"]["mean"]
+        achieved_gbs = hv["ok_ops_per_step"] * bpo / (kavg * 1e-3) / 1e9
+        traffic = TRAFFIC_PROFILE.get(head)
+        out["roofline"] = {
             "bound": "hbm",
             "achieved": achieved_gbs,
             "peak": HBM_PEAK_GBS,
@@ -802,72 +888,73 @@ def main():
                         kernel_sources_hash() == traffic["sources_sha256_16"] and
                         args.ticket_group in (0, 1024) and args.slot_mode == "linear" and
                         not args.fenced else None),
-            "kernel": (f"k_mix<{NAMES[dom]}>" if args.ticket_group == 64
-                       else f"k_mix_group<{NAMES[dom]}>"),
+            "kernel": hv["kernel"],
+            "kernel_ms_avg": kavg,
             "bytes_per_ok_op": bpo,
-        },
-    }
+            "ok_ops_per_launch": hv["ok_ops_per_step"],
+        }
     if (kernel_sources_hash() == COUNTER_SOURCES_HASH and args.ticket_group in (0, 1024)
             and args.slot_mode == "linear" and not args.fenced):
         out["profile_counters"] = {NAMES[k]: COUNTER_PROFILE[k] for k in kinds}
         out["profile_counters"]["profile"] = _COUNTERS
     if not args.no_probes:
-        p = measure_probes(gq, torch)
-        # Each of the four ticket counters serves one of every two operations
-        # (enqueues: fq.Head, aq.Tail; dequeues: aq.Head, fq.Tail), and one
-        # ticket FAA covers the a lanes of a ticket group taking the same
-        # branch (a = group / 2 at a 50/50 mix: 32 for one wavefront, 512
-        # for the default 1024-lane group).  Each successful op performs
-        # RMW_PER_OP_KIND atomic RMWs at the layout's stride.
-        group = args.ticket_group or 1024
-        a = group / 2.0
-        r_slot = p["r_slot_cas_linear_per_s" if args.slot_mode == "linear" else "r_slot_cas_per_s"]
-        per_kernel = {}
-        for k in kinds:
-            b = min(2 * a * p["r_ctr_wave_faa_per_s"], r_slot / RMW_PER_OP_KIND[k],
-                    p["hbm_copy_gbs"] * 1e9 / BYTES_PER_OP_KIND[k])
-            per_kernel[NAMES[k]] = {"bound_mops": b / 1e6,
-                                    "frac": variants[k]["mops"] * 1e6 / b}
-        bound_ops = per_kernel[NAMES[dom]]["bound_mops"] * 1e6
-        out["atomic_roofline"] = dict(p, ticket_group=group, lanes_per_faa=a,
-                                      bound_mops=bound_ops / 1e6, kernel=NAMES[dom],
-                                      frac=dv["mops"] * 1e6 / bound_ops, per_kernel=per_kernel)
-    for q in queues.values():
-        q.close()
-    queues.clear()
+        def probes():
+            p = measure_probes(gq, torch)
+            # Each of the four ticket counters serves one of every two
+            # operations (enqueues: fq.Head, aq.Tail; dequeues: aq.Head,
+            # fq.Tail), and one ticket FAA covers the a lanes of a ticket group
+            # taking the same branch (a = group / 2 at a 50/50 mix: 32 for one
+            # wavefront, 512 for the default 1024-lane group).  Each successful
+            # op performs RMW_PER_OP_KIND atomic RMWs at the layout's stride.
+            group = args.ticket_group or 1024
+            a = group / 2.0
+            r_slot = p["r_slot_cas_linear_per_s" if args.slot_mode == "linear"
+                       else "r_slot_cas_per_s"]
+            per_kernel = {}
+            for k in kinds:
+                if "error" in variants[k]:
+                    continue
+                b = min(2 * a * p["r_ctr_wave_faa_per_s"], r_slot / RMW_PER_OP_KIND[k],
+                        p["hbm_copy_gbs"] * 1e9 / BYTES_PER_OP_KIND[k])
+                per_kernel[NAMES[k]] = {"bound_mops": b / 1e6,
+                                        "frac": variants[k]["mops_kernel"] * 1e6 / b}
+            return dict(p, ticket_group=group, lanes_per_faa=a, per_kernel=per_kernel)
+        section(out, "atomic_roofline", probes)
     torch.cuda.empty_cache()
     if not args.no_ablation:
-        out["ticket_ablation"] = bench_ticket_ablation(gq, torch, kinds, base_seed, args)
+        section(out, "ticket_ablation",
+                lambda: bench_ticket_ablation(gq, torch, kinds, base_seed, args))
     if not args.no_c2:
-        out["c2_sweep"] = bench_c2(gq, torch, kinds, base_seed, args)
+        section(out, "c2_sweep", lambda: bench_c2(gq, torch, kinds, base_seed, args))
     if not args.no_timed:
-        out["fixed_duration"] = bench_timed(gq, torch, kinds)
+        section(out, "fixed_duration", lambda: bench_timed(gq, torch, kinds))
     if not args.no_multi:
-        out["batched_multi_queue"] = bench_multi(gq, torch)
-        log(f"[bench] multi: {out['batched_multi_queue']}")
+        section(out, "batched_multi_queue", lambda: bench_multi(gq, torch))
     if not args.no_c3:
-        out["imbalanced_prodcons"] = bench_c3(gq, torch)
-        from paper_2606_01693_amd import autotune
-        t = autotune.tune_prodcons("wfq", prod_waves=128, log2_inv_p=1,
-                                   patience_options=((16, 64), (64, 256), (256, 1024)),
-                                   help_delays=(64,), time_limit_ms=5000)
-        out["imbalanced_prodcons"]["wfq_patience_tuning_128_896_p_half"] = {
-            "best": t.best, "best_ms": t.best_ms, "table": t.table}
-        log(f"[bench] c3 G-WFQ patience tuning 128:896 p=1/2: best {t.best} {t.best_ms:.1f} ms")
+        def c3():
+            r = bench_c3(gq, torch)
+            from paper_2606_01693_amd import autotune
+            t = autotune.tune_prodcons("wfq", prod_waves=128, log2_inv_p=1,
+                                       patience_options=((16, 64), (64, 256), (256, 1024)),
+                                       help_delays=(64,), time_limit_ms=5000)
+            r["wfq_patience_tuning_128_896_p_half"] = {"best": t.best, "best_ms": t.best_ms,
+                                                       "table": t.table}
+            return r
+        section(out, "imbalanced_prodcons", c3)
     if not args.no_bfs:
-        out["bfs"] = bench_bfs(gq, torch)
+        section(out, "bfs", lambda: bench_bfs(gq, torch))
     if not args.no_serve:
-        out["serve"] = bench_serve(gq, torch)
+        section(out, "serve", lambda: bench_serve(gq, torch))
     if not args.no_rt:
-        out["raytrace"] = bench_rt(gq, torch)
+        section(out, "raytrace", lambda: bench_rt(gq, torch))
     if not args.no_cpu:
-        replay, locked = cpu_baselines(base_seed, LANES)
-        out["cpu_baseline"] = replay
-        out["cpu_locked_queue"] = locked
-        out["host"] = {"cpu": platform.processor() or platform.machine(),
-                       "cores": os.cpu_count()}
-    for q in queues.values():
-        q.close()
+        def cpu():
+            replay, locked = cpu_baselines(base_seed, LANES)
+            out["cpu_baseline"] = replay
+            out["host"] = {"cpu": platform.processor() or platform.machine(),
+                           "cores": os.cpu_count()}
+            return locked
+        section(out, "cpu_locked_queue", cpu)
     print(json.dumps(out), flush=True)
 
 

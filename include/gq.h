@@ -130,6 +130,8 @@ typedef struct gq_dev {
     uint32_t help_delay;       /* G-WFQ help delay D                          */
     uint32_t group_lanes;      /* gq_options.ticket_group (resolved)          */
     uint32_t *help_ctr;        /* G-WFQ per-lane <next peer:20 | ops:12>      */
+    uint8_t *ymc_hint;         /* G-WFQ-YMC per-lane "last dequeue found the
+                                  queue empty" bytes, else NULL               */
 } gq_dev;
 
 typedef struct gq_stats {
@@ -140,6 +142,11 @@ typedef struct gq_stats {
     uint64_t slow_enter;       /* G-WFQ / YMC slow-path entries               */
     uint64_t helps;            /* peer requests helped                        */
     uint64_t scans;            /* G-WFQ record scans to finalize an enqueue   */
+    uint64_t dropped;          /* operations a device fail-safe bound stopped
+                                  (error latched): an enqueue so stopped
+                                  reports GQ_ERR_DEVICE and its item is lost;
+                                  a dequeue that already took its item still
+                                  reports GQ_OK, its free index being lost  */
 } gq_stats;
 
 /* Bytes of device memory a queue with these parameters needs.
@@ -173,7 +180,9 @@ gq_status gq_reset(gq_queue *q, void *stream);
 
 /* Batched enqueue: m items (item_width bytes each, contiguous) from d_items,
  * each tried once by its own lane, concurrently, with no order among them.
- * d_status (nullable): one byte per item, GQ_OK or GQ_FULL.
+ * d_status (nullable): one byte per item, GQ_OK or GQ_FULL; an operation that
+ * a device fail-safe bound stopped (the queue's error is latched, see
+ * gq_stats.dropped) stores the low byte of its negative gq_status.
  * d_num_ok (nullable): a device uint64 to which the OK count is ADDED.
  * Batches issued on one stream take effect in stream order.  The first
  * ticket of each operation is taken once per gq_options.ticket_group lanes.  */

@@ -269,6 +269,41 @@ __device__ __forceinline__ void latch_error(uint64_t* err, uint64_t code) {
 }
 
 // Statistics slots (gq_stats order).
-enum StatSlot { S_OK_ENQ = 0, S_OK_DEQ, S_FULL, S_EMPTY, S_CAS_FAIL, S_TICKETS, S_SLOW, S_HELPS, S_SCAN, S_NUM };
+enum StatSlot {
+  S_OK_ENQ = 0, S_OK_DEQ, S_FULL, S_EMPTY, S_CAS_FAIL, S_TICKETS, S_SLOW, S_HELPS, S_SCAN,
+  S_DROP,  // operations abandoned by a fail-safe bound (item or index lost, error latched)
+  S_NUM
+};
+
+// Fail-safe bound of every retry loop in the queues.  The algorithms retry
+// only while other lanes make progress, so reaching SPIN_LIMIT iterations
+// means an invariant broke.  Once any lane has latched an error on the queue
+// (a broken invariant, an exhausted pool, or a driver's time limit) every
+// loop also stops within SPIN_POLL iterations: then no kernel that uses the
+// queue can stay inside a queue operation after its driver gave up.
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+constexpr uint32_t SPIN_POLL = 1024;
+__device__ __forceinline__ bool spin_out(uint32_t spin, const uint64_t* err) {
+  if (spin >= SPIN_LIMIT) return true;
+  return (spin & (SPIN_POLL - 1)) == SPIN_POLL - 1 &&
+         __hip_atomic_load(err, __ATOMIC_RELAXED, GQ_AGENT) != 0;
+}
+
+// Entries a dequeuer could find right now on a pair of monotone ticket
+// counters: Tail - Head, read in that order (Head first, and only after its
+// value has returned, Tail), or 0 when Tail <= Head.  Both counters sit in
+// the bits above `shift` of their words.  With Tail <= Head every item
+// already in the queue was handed a Head ticket before the Tail read, so the
+// dequeuers holding those tickets will take them: they can be linearized
+// just before the Tail read, in ticket order, and the queue is empty there --
+// an EMPTY answer that takes (and burns) no ticket.
+__device__ __forceinline__ uint64_t poll_avail(uint64_t* head, uint64_t* tail, uint32_t shift) {
+  const uint64_t hh = read_first_lane(ld(head));
+  keep(hh);
+  wait_mem();
+  const uint64_t tt = read_first_lane(ld(tail));
+  const uint64_t hc = hh >> shift, tc = tt >> shift;
+  return tc > hc ? tc - hc : 0;
+}
 
 }  // namespace gq

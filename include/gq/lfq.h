@@ -20,13 +20,12 @@ namespace lfq {
 
 constexpr uint32_t BOT = 0xFFFFFFFFu;   // empty slot
 constexpr uint32_t BOTC = 0xFFFFFFFEu;  // consumed slot
+// Result of an inner dequeue stopped by the fail-safe bound (error latched);
+// never a valid index (indices are below n <= 2^30).
+constexpr uint32_t GAVE_UP = 0xFFFFFFFDu;
 constexpr uint32_t CYC_BITS = 31;
 constexpr uint32_t CYC_MASK = (1u << CYC_BITS) - 1u;
 constexpr uint32_t CYC_HALF = 1u << (CYC_BITS - 1);
-// Fail-safe bound on retries of one inner operation.  Reaching it means an
-// invariant broke (the algorithm retries only while other lanes progress);
-// the operation then latches GQ_ERR_DEVICE and gives up instead of spinning.
-constexpr uint32_t SPIN_LIMIT = 1u << 22;
 
 __device__ __forceinline__ uint32_t e_idx(uint64_t e) { return (uint32_t)e; }
 __device__ __forceinline__ bool e_safe(uint64_t e) { return (e >> 32) & 1u; }
@@ -106,8 +105,10 @@ __device__ __forceinline__ void catchup(const Ring& r, uint64_t target) {
 }
 
 // Inner enqueue of index `idx` (Algorithm 1, TryEnq, retried until success).
-// RELEASE makes the install CAS an agent-scope release (fenced hand-off).  An index ring never holds more than
-// n indices in 2n slots, so the retry loop ends (lock-freedom, Section III-B).
+// RELEASE makes the install CAS an agent-scope release (fenced hand-off).  An
+// index ring never holds more than n indices in 2n slots, so the retry loop
+// ends (lock-freedom, Section III-B).  Returns false only when the fail-safe
+// bound (spin_out) stopped it: the index was not installed.
 // `first`: a Tail ticket already reserved for this operation (workgroup
 // aggregation), used for the first attempt; GROUP_NONE to take one here.
 template <bool RELEASE>
@@ -115,9 +116,9 @@ __device__ __forceinline__ bool ring_enq(const Ring& r, uint32_t idx, uint32_t& 
                                          uint64_t* err, uint64_t first = GROUP_NONE) {
   bool done = false;
   for (uint32_t spin = 0; !done; spin++) {
-    if (spin >= SPIN_LIMIT) {
+    if (spin_out(spin, err)) {
       latch_error(err, (uint64_t)(-GQ_ERR_DEVICE));
-      return false;
+      return false;  // the index is lost: the caller reports the drop
     }
     uint64_t t;
     if (first != GROUP_NONE) {
@@ -147,28 +148,14 @@ __device__ __forceinline__ bool ring_enq(const Ring& r, uint32_t idx, uint32_t& 
   return true;
 }
 
-// Entries a dequeuer could find right now: Tail - Head, read in that order
-// (Head first, and only after its value has returned, Tail), or 0 when Tail
-// <= Head.  Both counters sit in the bits above `shift` of their words.
-// Head and Tail only grow.  With Tail <= Head, every installed entry's
-// ticket is below Head, so a dequeuer already holds it and will consume it:
-// those dequeuers can be linearized just before the Tail read, in ticket
-// order, and the queue is empty there -- an EMPTY answer that takes (and
-// burns) no ticket.  When fewer entries than polling lanes are available,
-// only that many lanes of a wavefront take tickets; the others look again
-// instead of taking tickets past Tail, each of which would mark a slot and
-// make Tail catch up.
-__device__ __forceinline__ uint64_t poll_avail(uint64_t* head, uint64_t* tail, uint32_t shift) {
-  const uint64_t hh = read_first_lane(ld(head));
-  keep(hh);
-  wait_mem();
-  const uint64_t tt = read_first_lane(ld(tail));
-  const uint64_t hc = hh >> shift, tc = tt >> shift;
-  return tc > hc ? tc - hc : 0;
-}
+// poll_avail (common.h) is the empty pre-check of ring_deq: when fewer
+// entries than polling lanes are available, only that many lanes of a
+// wavefront take tickets; the others look again instead of taking tickets
+// past Tail, each of which would mark a slot and make Tail catch up.
 
 // Inner dequeue (Algorithm 1, TryDeq, retried until an index or EMPTY).
-// Returns the index, or BOT for EMPTY.  ACQUIRE makes Consume an agent-scope
+// Returns the index, BOT for EMPTY, or GAVE_UP when the fail-safe bound
+// stopped it (error latched).  ACQUIRE makes Consume an agent-scope
 // acquire (fenced hand-off).  Consume is an atomic XOR that turns
 // the index field into BOTC and leaves Cycle/Safe alone; between install and
 // consume only Safe can change, so the XOR is exact.
@@ -181,9 +168,9 @@ template <bool ACQUIRE>
 __device__ __forceinline__ uint32_t ring_deq(const Ring& r, uint32_t& cas_fail, uint64_t* err,
                                              uint64_t first = GROUP_NONE) {
   for (uint32_t spin = 0;; spin++) {
-    if (spin >= SPIN_LIMIT) {
+    if (spin_out(spin, err)) {
       latch_error(err, (uint64_t)(-GQ_ERR_DEVICE));
-      return BOT;
+      return GAVE_UP;
     }
     uint64_t h;
     if (first != GROUP_NONE) {
@@ -287,6 +274,13 @@ __device__ __forceinline__ uint64_t payload_get(const gq_dev& q, uint32_t idx) {
 // ---- outer queue (Section III-B: indices move through aq/fq) -------------
 // enqueue: idx <- fq.deq (EMPTY means FULL); data[idx] <- x; aq.enq(idx).
 // dequeue: idx <- aq.deq (EMPTY means EMPTY); x <- data[idx]; fq.enq(idx).
+// A fail-safe stop of the second inner operation (ring_enq gave up, error
+// latched) loses the index: an enqueue then reports GQ_ERR_DEVICE (its item
+// is lost with the index); a dequeue keeps its item (it was read before) and
+// reports GQ_OK, the lost free index shrinking the queue.  Both count one
+// drop.
+__device__ __forceinline__ void count_drop(const gq_dev& q) { faa(q.stats + S_DROP, 1ull); }
+
 template <bool FENCED>
 __device__ __forceinline__ int enqueue_impl(const gq_dev& q, uint64_t item, uint32_t& cas_fail) {
   const Ring fq = make_ring(q.fq, q);
@@ -295,12 +289,16 @@ __device__ __forceinline__ int enqueue_impl(const gq_dev& q, uint64_t item, uint
   // finished reading the cell before releasing idx into fq: no acquire needed.
   const uint32_t idx = ring_deq<false>(fq, cas_fail, q.err);
   if (idx == BOT) return GQ_FULL;
-  if (idx >= q.capacity) {  // never taken: guards the payload array
+  if (idx >= q.capacity) {  // GAVE_UP; guards the payload array
     latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
-    return GQ_FULL;
+    count_drop(q);
+    return GQ_ERR_DEVICE;
   }
   payload_put<FENCED>(q, idx, item);
-  ring_enq<FENCED>(aq, idx, cas_fail, q.err);
+  if (!ring_enq<FENCED>(aq, idx, cas_fail, q.err)) {
+    count_drop(q);
+    return GQ_ERR_DEVICE;
+  }
   return GQ_OK;
 }
 
@@ -310,12 +308,13 @@ __device__ __forceinline__ int dequeue_impl(const gq_dev& q, uint64_t* item, uin
   const Ring fq = make_ring(q.fq, q);
   const uint32_t idx = ring_deq<FENCED>(aq, cas_fail, q.err);
   if (idx == BOT) return GQ_EMPTY;
-  if (idx >= q.capacity) {  // never taken: guards the payload array
+  if (idx >= q.capacity) {  // GAVE_UP; guards the payload array
     latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
-    return GQ_EMPTY;
+    count_drop(q);
+    return GQ_ERR_DEVICE;
   }
   *item = payload_get<FENCED>(q, idx);
-  ring_enq<FENCED>(fq, idx, cas_fail, q.err);
+  if (!ring_enq<FENCED>(fq, idx, cas_fail, q.err)) count_drop(q);
   return GQ_OK;
 }
 
@@ -339,11 +338,13 @@ __device__ __forceinline__ int group_op_impl(const gq_dev& q, int role, uint64_t
   uint32_t idx = BOT;
   if (wf) idx = ring_deq<false>(fq, cas_fail, q.err, t);
   else if (wa) idx = ring_deq<FENCED>(aq, cas_fail, q.err, t);
-  if (idx != BOT && idx >= q.capacity) {  // never taken: guards the payload array
-    latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
-    idx = BOT;
-  }
   int st = role == ROLE_ENQ ? GQ_FULL : role == ROLE_DEQ ? GQ_EMPTY : GQ_OK;
+  if (idx != BOT && idx >= q.capacity) {  // GAVE_UP; guards the payload array
+    latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
+    count_drop(q);
+    idx = BOT;
+    st = GQ_ERR_DEVICE;
+  }
   if (idx != BOT) {
     if (role == ROLE_ENQ) payload_put<FENCED>(q, idx, item);
     else item = payload_get<FENCED>(q, idx);
@@ -352,8 +353,13 @@ __device__ __forceinline__ int group_op_impl(const gq_dev& q, int role, uint64_t
   const bool we = role == ROLE_ENQ && idx != BOT;
   const bool wd = role == ROLE_DEQ && idx != BOT;
   t = group_ticket(s, par, aq.tail, 1, we, fq.tail, 1, wd);
-  if (we) ring_enq<FENCED>(aq, idx, cas_fail, q.err, t);
-  else if (wd) ring_enq<FENCED>(fq, idx, cas_fail, q.err, t);
+  bool placed = true;
+  if (we) placed = ring_enq<FENCED>(aq, idx, cas_fail, q.err, t);
+  else if (wd) placed = ring_enq<FENCED>(fq, idx, cas_fail, q.err, t);
+  if (!placed) {
+    count_drop(q);
+    if (we) st = GQ_ERR_DEVICE;
+  }
   return st;
 }
 

@@ -41,6 +41,7 @@ namespace wfq {
 
 using lfq::BOT;
 using lfq::BOTC;
+using lfq::GAVE_UP;
 using lfq::idx_free;
 
 constexpr uint32_t TAG_BITS = 15;
@@ -56,13 +57,13 @@ constexpr uint64_t TID_MASK = (1ull << TID_BITS) - 1;
 constexpr uint64_t UNIT = 1ull << TID_BITS;        // one ticket on the Global word
 constexpr uint64_t CTR_MASK = (1ull << 44) - 1;   // 44-bit counters
 constexpr uint64_t NO_TICKET = CTR_MASK;          // "no fast-path ticket taken"
+constexpr uint64_t SLOW_GAVE_UP = CTR_MASK - 1;   // run_slow stopped by a fail-safe bound
 
 constexpr uint64_t L_FIN = 1;
 constexpr uint64_t L_INC = 2;
 constexpr uint32_t L_TAG_SHIFT = 46;
 constexpr uint64_t L_TAG_MASK = (1ull << 18) - 1;
 
-constexpr uint32_t SPIN_LIMIT = 1u << 22;
 // Looks a dequeuer takes at an entry whose enqueuer holds the ticket but has
 // not installed yet (see try_deq).
 constexpr uint32_t DEQ_WAIT_POLLS = 64;
@@ -147,7 +148,7 @@ __device__ __forceinline__ void reset_threshold(const WRing& r) {
 __device__ __forceinline__ void catchup(const WRing& r, uint64_t target) {
   uint64_t g = ld(r.g.tail);
   for (uint32_t spin = 0; g_ctr(g) < target; spin++) {
-    if (spin >= SPIN_LIMIT) { latch_error(r.err, (uint64_t)(-GQ_ERR_DEVICE)); return; }
+    if (spin_out(spin, r.err)) { latch_error(r.err, (uint64_t)(-GQ_ERR_DEVICE)); return; }
     if (cas(r.g.tail, g, (target << TID_BITS) | g_thr(g))) return;
   }
 }
@@ -288,7 +289,7 @@ __device__ __forceinline__ void clear_thr(const WRing& r, uint64_t* G, uint32_t 
   Rec* R2 = &r.rec[q2];
   uint64_t g = ld_acq(G);
   for (uint32_t spin = 0; g_thr(g) == q2 + 1; spin++) {
-    if (spin >= SPIN_LIMIT) { latch_error(r.err, (uint64_t)(-GQ_ERR_DEVICE)); return; }
+    if (spin_out(spin, r.err)) { latch_error(r.err, (uint64_t)(-GQ_ERR_DEVICE)); return; }
     const uint64_t l2 = ld_acq(&R2->local);
     if (l_inc(l2)) {
       if (l_ctr(l2) >= g_ctr(g)) {  // stale view of Global: read it again
@@ -304,15 +305,17 @@ __device__ __forceinline__ void clear_thr(const WRing& r, uint64_t* G, uint32_t 
 
 // SlowFAA (Algorithm 2): returns true with v = the Local word holding the
 // next agreed ticket, or false once the request is finished (FIN) or replaced
-// (tag changed).  thld: Threshold for dequeue rounds (decremented once per
-// round by the helper whose increment succeeded), NULL for enqueues.
+// (tag changed), or when a fail-safe bound stopped it (gave_up set, error
+// latched).  thld: Threshold for dequeue rounds (decremented once per round by
+// the helper whose increment succeeded), NULL for enqueues.
 __device__ __forceinline__ bool slow_faa(const WRing& r, uint64_t* G, uint32_t rid, uint64_t tag,
                                          uint64_t& v, int64_t* thld, uint64_t deadline,
-                                         bool* announced) {
+                                         bool* announced, bool& gave_up) {
   Rec* R = &r.rec[rid];
   for (uint32_t spin = 0;; spin++) {
-    if (spin >= SPIN_LIMIT || ((spin & 255) == 255 && stamp() > deadline)) {
+    if (spin_out(spin, r.err) || ((spin & 255) == 255 && stamp() > deadline)) {
       latch_error(r.err, (uint64_t)(-GQ_ERR_DEVICE));
+      gave_up = true;
       return false;
     }
     if (announced && !*announced && (spin & 63) == 63) *announced = try_announce(r, rid);
@@ -353,22 +356,23 @@ __device__ __forceinline__ void hint_owner(const WRing& r, uint64_t j, uint64_t 
     if (cas(&r.owner[j], o, nw)) break;
 }
 
-// TryEnqSlow on the agreed ticket T.  Returns true when the request's item is
-// installed at T (by this or another helper), false to go to the next round.
-__device__ __forceinline__ bool try_enq_slow(const WRing& r, uint64_t T, uint32_t idx, uint32_t rid,
-                                             uint64_t tag) {
+// TryEnqSlow on the agreed ticket T.  Returns 1 when the request's item is
+// installed at T (by this or another helper), 0 to go to the next round, -1
+// when the fail-safe bound stopped it (error latched).
+__device__ __forceinline__ int try_enq_slow(const WRing& r, uint64_t T, uint32_t idx, uint32_t rid,
+                                            uint64_t tag) {
   const uint32_t c = r.cycle_of(T);
   const uint64_t j = r.slot_of(T);
   uint64_t* p = r.g.at(j);
   uint64_t e = ld_acq(p);
   for (uint32_t spin = 0;; spin++) {
-    if (spin >= SPIN_LIMIT) { latch_error(r.err, (uint64_t)(-GQ_ERR_DEVICE)); return true; }
-    if (e_cyc(e) == c) return e_idx(e) != BOT;  // ours (maybe consumed), or dequeuer T left it empty
-    if (!older(e_cyc(e), c) || !older(e_note(e), c)) return false;  // moved on, or already noted
+    if (spin_out(spin, r.err)) { latch_error(r.err, (uint64_t)(-GQ_ERR_DEVICE)); return -1; }
+    if (e_cyc(e) == c) return e_idx(e) != BOT ? 1 : 0;  // ours (maybe consumed), or dequeuer T left it empty
+    if (!older(e_cyc(e), c) || !older(e_note(e), c)) return 0;  // moved on, or already noted
     if (!((e_safe(e) || g_ctr(ld(r.g.head)) <= T) && idx_free(e_idx(e)))) {
       // Lemma 6: record that this slot is ruled out for cycle c
       const uint64_t ne = (e & ~((uint64_t)TAG_MASK << NOTE_SHIFT)) | ((uint64_t)c << NOTE_SHIFT);
-      if (cas_acqrel(p, e, ne)) return false;
+      if (cas_acqrel(p, e, ne)) return 0;
       continue;
     }
     hint_owner(r, j, T, rid);
@@ -383,7 +387,7 @@ __device__ __forceinline__ bool try_enq_slow(const WRing& r, uint64_t T, uint32_
           if (cas_acqrel(p, e2, e2 | ENQ_BIT)) break;
       }
       reset_threshold(r);
-      return true;
+      return 1;
     }
   }
 }
@@ -401,7 +405,7 @@ __device__ __forceinline__ bool try_deq_slow(const WRing& r, uint64_t H, uint32_
   uint64_t* p = r.g.at(r.slot_of(H));
   uint64_t e = ld_acq(p);
   for (uint32_t spin = 0;; spin++) {
-    if (spin >= SPIN_LIMIT) { latch_error(r.err, (uint64_t)(-GQ_ERR_DEVICE)); return true; }
+    if (spin_out(spin, r.err)) { latch_error(r.err, (uint64_t)(-GQ_ERR_DEVICE)); return true; }
     if (e_cyc(e) == c && e_idx(e) != BOT) {
       fin_at(R, tag, H);
       return true;
@@ -432,7 +436,9 @@ __device__ __forceinline__ bool try_deq_slow(const WRing& r, uint64_t H, uint32_
 // (starting another round then would install it twice) and returns that
 // ticket.  A dequeue keeps going until FIN: helpers may disagree about an
 // empty decision, and the request follows whichever change of its Local word
-// lands first.  Returns NO_TICKET when the request was found finished.
+// lands first.  Returns NO_TICKET when the request was found finished, and
+// SLOW_GAVE_UP when a fail-safe bound stopped this lane's part (error
+// latched).
 __device__ __forceinline__ uint64_t run_slow(const WRing& r, uint32_t rid, uint64_t tag, bool is_enq,
                                              uint32_t idx, uint64_t v, bool* announced = nullptr) {
   uint64_t* G = is_enq ? r.g.tail : r.g.head;
@@ -441,19 +447,23 @@ __device__ __forceinline__ uint64_t run_slow(const WRing& r, uint32_t rid, uint6
   // the GPU clock latches GQ_ERR_DEVICE instead of occupying its lane longer
   // (the bound Lemma 4 gives is far shorter in every configuration tested).
   const uint64_t deadline = stamp() + SLOW_LIMIT_TICKS;
-  for (uint32_t rounds = 0; slow_faa(r, G, rid, tag, v, thld, deadline, announced); rounds++) {
-    if (rounds >= SPIN_LIMIT || stamp() > deadline) {
+  bool gave_up = false;
+  for (uint32_t rounds = 0; slow_faa(r, G, rid, tag, v, thld, deadline, announced, gave_up);
+       rounds++) {
+    if (spin_out(rounds, r.err) || stamp() > deadline) {
       latch_error(r.err, (uint64_t)(-GQ_ERR_DEVICE));
-      return NO_TICKET;
+      return SLOW_GAVE_UP;
     }
     const uint64_t T = l_ctr(v);
     if (is_enq) {
-      if (try_enq_slow(r, T, idx, rid, tag)) return T;
+      const int res = try_enq_slow(r, T, idx, rid, tag);
+      if (res > 0) return T;
+      if (res < 0) return SLOW_GAVE_UP;
     } else {
       try_deq_slow(r, T, rid, tag);
     }
   }
-  return NO_TICKET;
+  return gave_up ? SLOW_GAVE_UP : NO_TICKET;
 }
 
 // Publish a request (Section III-C, "GPU publication discipline"): payload
@@ -526,18 +536,20 @@ __device__ __forceinline__ void help_check(const gq_dev& q, uint32_t tid) {
 // Inner enqueue of idx: fast path up to patience_enq attempts, then the slow path.
 // `first`: a Tail ticket already reserved for this operation (workgroup
 // aggregation), tried before the fast-path loop; NO_TICKET if none.
+// Returns false only when a fail-safe bound stopped the slow path before the
+// index was installed (error latched).
 template <bool RELEASE>
-__device__ __forceinline__ void ring_enq(const WRing& r, const gq_dev& q, uint32_t tid, uint32_t idx,
+__device__ __forceinline__ bool ring_enq(const WRing& r, const gq_dev& q, uint32_t tid, uint32_t idx,
                                          uint32_t& cf, uint64_t first = NO_TICKET) {
   uint64_t last = NO_TICKET;
   if (first != NO_TICKET) {
-    if (try_enq<RELEASE>(r, first, idx, cf)) return;
+    if (try_enq<RELEASE>(r, first, idx, cf)) return true;
     last = first;
   }
   for (uint32_t a = first != NO_TICKET ? 1u : 0u; a < q.patience_enq; a++) {
     help_announced(r, tid);
     const uint64_t t = ticket(wave_faa(r.g.tail, UNIT));
-    if (try_enq<RELEASE>(r, t, idx, cf)) return;
+    if (try_enq<RELEASE>(r, t, idx, cf)) return true;
     last = t;
   }
   faa(r.stats + S_SLOW, 1ull);
@@ -546,7 +558,7 @@ __device__ __forceinline__ void ring_enq(const WRing& r, const gq_dev& q, uint32
   const uint64_t tag = publish(R, true, last, idx, seq, v0);
   bool announced = try_announce(r, tid);
   const uint64_t T = run_slow(r, tid, tag, true, idx, v0, &announced);
-  if (T != NO_TICKET) {
+  if (T != NO_TICKET && T != SLOW_GAVE_UP) {
     // The item sits at T; make sure FIN is set and the entry is ordinary
     // before the record is reused (otherwise a dequeuer meeting Enq = 0
     // would have to scan every record for the finished request).
@@ -559,9 +571,11 @@ __device__ __forceinline__ void ring_enq(const WRing& r, const gq_dev& q, uint32
   }
   if (announced) withdraw(r, tid);
   unpublish(R, true, seq);
+  return T != SLOW_GAVE_UP;
 }
 
-// Inner dequeue: returns an index or BOT (EMPTY).
+// Inner dequeue: returns an index, BOT (EMPTY), or GAVE_UP when a fail-safe
+// bound stopped the slow path (error latched).
 // `first`: a Head ticket already reserved for this operation (workgroup
 // aggregation; Threshold was checked before reserving it).  It is always
 // tried: a Head ticket that no dequeuer visits could strand an item.
@@ -581,10 +595,10 @@ __device__ __forceinline__ uint32_t ring_deq(const WRing& r, const gq_dev& q, ui
     help_announced(r, tid);
     // empty pre-check and bounded grab on the counters while Threshold shows
     // recent failures or this lane's last dequeue here found the ring empty
-    // (see lfq::ring_deq and lfq::poll_avail)
+    // (see lfq::ring_deq and poll_avail)
     const bool hinted = r.hint[tid] != 0;
     if (th < r.g.thr_reset || hinted) {
-      const uint64_t avail = lfq::poll_avail(r.g.head, r.g.tail, TID_BITS);
+      const uint64_t avail = poll_avail(r.g.head, r.g.tail, TID_BITS);
       if (avail == 0) {
         if (!hinted) r.hint[tid] = 1;
         return BOT;
@@ -609,9 +623,9 @@ __device__ __forceinline__ uint32_t ring_deq(const WRing& r, const gq_dev& q, ui
   const uint64_t l = ld_acq(&R->local);
   if (announced) withdraw(r, tid);
   unpublish(R, false, seq);
-  if (!l_fin(l) || l_tag(l) != (tag & L_TAG_MASK)) {  // never: the loop ends on FIN
+  if (!l_fin(l) || l_tag(l) != (tag & L_TAG_MASK)) {  // only after a fail-safe stop
     latch_error(r.err, (uint64_t)(-GQ_ERR_DEVICE));
-    return BOT;
+    return GAVE_UP;
   }
   const uint64_t H = l_ctr(l);
   const uint64_t j = r.slot_of(H);
@@ -639,12 +653,16 @@ __device__ __forceinline__ int enqueue_impl(const gq_dev& q, uint64_t item, uint
   const WRing aq = make_wring(q.aq, q);
   const uint32_t idx = ring_deq<false>(fq, q, tid, cf);
   if (idx == BOT) return GQ_FULL;
-  if (idx >= q.capacity) {
+  if (idx >= q.capacity) {  // GAVE_UP; guards the payload array
     latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
-    return GQ_FULL;
+    lfq::count_drop(q);
+    return GQ_ERR_DEVICE;
   }
   lfq::payload_put<FENCED>(q, idx, item);
-  ring_enq<FENCED>(aq, q, tid, idx, cf);
+  if (!ring_enq<FENCED>(aq, q, tid, idx, cf)) {  // the item is lost with its index
+    lfq::count_drop(q);
+    return GQ_ERR_DEVICE;
+  }
   return GQ_OK;
 }
 
@@ -660,12 +678,13 @@ __device__ __forceinline__ int dequeue_impl(const gq_dev& q, uint64_t* item, uin
   const WRing fq = make_wring(q.fq, q);
   const uint32_t idx = ring_deq<FENCED>(aq, q, tid, cf);
   if (idx == BOT) return GQ_EMPTY;
-  if (idx >= q.capacity) {
+  if (idx >= q.capacity) {  // GAVE_UP; guards the payload array
     latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
-    return GQ_EMPTY;
+    lfq::count_drop(q);
+    return GQ_ERR_DEVICE;
   }
   *item = lfq::payload_get<FENCED>(q, idx);
-  ring_enq<FENCED>(fq, q, tid, idx, cf);
+  if (!ring_enq<FENCED>(fq, q, tid, idx, cf)) lfq::count_drop(q);  // the item was delivered
   return GQ_OK;
 }
 
@@ -693,9 +712,11 @@ __device__ __forceinline__ int group_op_impl(const gq_dev& q, int role, uint64_t
   uint32_t idx = BOT;
   if (wf) idx = ring_deq<false>(fq, q, tid, cf, t);
   else if (wa) idx = ring_deq<FENCED>(aq, q, tid, cf, t);
-  if (idx != BOT && idx >= q.capacity) {
+  if (idx != BOT && idx >= q.capacity) {  // GAVE_UP; guards the payload array
     latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
+    lfq::count_drop(q);
     idx = BOT;
+    st = GQ_ERR_DEVICE;
   }
   if (idx != BOT) {
     if (role == ROLE_ENQ) lfq::payload_put<FENCED>(q, idx, item);
@@ -705,8 +726,13 @@ __device__ __forceinline__ int group_op_impl(const gq_dev& q, int role, uint64_t
   const bool we = role == ROLE_ENQ && idx != BOT;
   const bool wd = role == ROLE_DEQ && idx != BOT;
   t = group_decode(group_ticket(s, par, aq.g.tail, UNIT, we, fq.g.tail, UNIT, wd));
-  if (we) ring_enq<FENCED>(aq, q, tid, idx, cf, t);
-  else if (wd) ring_enq<FENCED>(fq, q, tid, idx, cf, t);
+  bool placed = true;
+  if (we) placed = ring_enq<FENCED>(aq, q, tid, idx, cf, t);
+  else if (wd) placed = ring_enq<FENCED>(fq, q, tid, idx, cf, t);
+  if (!placed) {
+    lfq::count_drop(q);
+    if (we) st = GQ_ERR_DEVICE;
+  }
   return st;
 }
 

@@ -28,7 +28,10 @@ extern "C" {
  * opst = op | (status << 1), op 0 = enqueue, 1 = dequeue; status as gq_status.
  * val is the enqueued argument or the dequeued value (0 for EMPTY).
  * call/ret are device real-time stamps (100 MHz) taken before the call and
- * after the operation's writes completed.                                     */
+ * after every memory access of the operation completed: with the default
+ * atomic hand-off every such access is a device-coherent atomic, so the lane
+ * only waits for them (as the unrecorded kernels' operations do); with
+ * GQ_OPT_FENCED the end stamp follows an agent-scope release.                */
 typedef struct gq_history {
     uint64_t *val;
     uint64_t *call;
@@ -40,14 +43,29 @@ typedef struct gq_history {
 } gq_history;
 
 /* Mixed workload (Section V-A micro-benchmark shape, fixed op count): each of
- * `lanes` lanes (a multiple of 64; workgroups of 256 when lanes allows, else 64)
- * performs ops_per_lane operations; op r of lane g is an enqueue when the top
- * bit of r(seed, (g << 32) | r) is 0, else a dequeue.  Each op is tried once:
- * FULL/EMPTY outcomes are counted, not retried.  Lane g's j-th successful
- * enqueue carries the token (g << 32) | (j + 1) (Section IV token format).
- * d_counts[4] += {ok_enq, ok_deq, full, empty}.  hist may be NULL.            */
+ * `lanes` lanes (a multiple of 64) performs ops_per_lane operations; op r of
+ * lane g is an enqueue when the top bit of r(seed, (g << 32) | r) is 0, else
+ * a dequeue.  Each op is tried once: FULL/EMPTY outcomes are counted, not
+ * retried.  Lane g's j-th successful enqueue carries the token
+ * (g << 32) | (j + 1) (Section IV token format).
+ * Launch: workgroups of the queue's ticket group (gq_options.ticket_group,
+ * 1024 lanes by default), halved until it divides `lanes`, every lane taking
+ * part in its workgroup's aggregated first tickets; a group of 64 lanes means
+ * per-wavefront tickets in workgroups of 256 lanes (64 when 256 does not
+ * divide `lanes`).
+ * d_counts[8] += {ok_enq, ok_deq, full, empty, S1_deq, S2_deq, S1_enq,
+ * S2_enq}: the wrapping (mod 2^64) sums of v and v * v over the items v
+ * dequeued (deq) and enqueued (enq) successfully, as in gq_run_prodcons.
+ * d_lane_enq (nullable): lane g's count of successful enqueues is stored at
+ * d_lane_enq[g], so its tokens are known without a history.  hist may be
+ * NULL; with a history the same work runs in a recording kernel.
+ * G-WFQ: all lanes must be co-resident (its wait-freedom assumes it, Section
+ * III-C), else GQ_ERR_RESIDENCY.  G-WFQ-YMC: a run that may need more cells
+ * than the pool holds (lanes * ops_per_lane > pool cells) is refused with
+ * GQ_ERR_POOL_EXHAUSTED before anything is launched.                         */
 gq_status gq_run_mix(gq_queue *q, uint64_t seed, uint32_t lanes, uint32_t ops_per_lane,
-                     uint64_t *d_counts, const gq_history *hist, void *stream);
+                     uint64_t *d_counts, uint32_t *d_lane_enq, const gq_history *hist,
+                     void *stream);
 
 /* ---- many independent queues in one launch ---------------------------------
  * A gq_multi binds nq queues of one kind; queue i gets lanes_per_queue[i]
@@ -56,8 +74,8 @@ gq_status gq_run_mix(gq_queue *q, uint64_t seed, uint32_t lanes, uint32_t ops_pe
  * workgroups of `block` (64, 128 or 256) lanes.  gq_multi_run_mix runs the
  * mixed workload (as gq_run_mix, ops_per_lane each, lane ids counted within
  * each queue, tokens and draws from the global lane id) on every queue in ONE
- * kernel launch; d_counts[4 * i + 0..3] += {ok_enq, ok_deq, full, empty} of
- * queue i.  gq_multi_capture records (seed bump + that launch) into a
+ * kernel launch; d_counts[8 * i + 0..7] += queue i's eight gq_run_mix
+ * counts {ok_enq, ok_deq, full, empty, S1_deq, S2_deq, S1_enq, S2_enq}.  gq_multi_capture records (seed bump + that launch) into a
  * hipGraph on `stream` (which must not be the legacy default stream);
  * gq_multi_replay launches it (each replay advances the seed by one).       */
 typedef struct gq_multi gq_multi;
@@ -101,10 +119,8 @@ gq_status gq_run_balanced(gq_queue *q, uint32_t lanes, uint32_t rounds, uint64_t
  * max_rounds bounds every lane's loop; exceeding it latches GQ_ERR_DEVICE.
  * time_limit_ms (0 = none) bounds the run's duration on the GPU clock: a lane
  * past it stops and latches GQ_ERR_DEVICE (a bounded wait, not a result).
- * With a history, only the first of each run of consecutive FULL (EMPTY)
- * answers of a lane is recorded: a failed operation has no effect, so the
- * recorded history is linearizable whenever the complete one is, and polling
- * lanes do not overflow it.
+ * With a history, every operation a lane performs is recorded, the polls that
+ * answer FULL or EMPTY included (size per_lane for them).
  * d_counts[8] += {ok_enq, ok_deq, full, empty, S1_deq, S2_deq, S1_enq,
  * S2_enq}, where S1 and S2 are the wrapping (mod 2^64) sums of v and v * v
  * over the items v successfully dequeued (deq) or enqueued (enq): multiset

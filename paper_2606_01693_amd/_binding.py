@@ -69,7 +69,7 @@ def make_options(slot_mode="linear", fenced=False, ymc_pool_cells=0, patience=No
 class _Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("ok_enq", "ok_deq", "full", "empty", "cas_fail", "tickets", "slow_enter",
-                 "helps", "scans")]
+                 "helps", "scans", "dropped")]
 
 
 class _History(ctypes.Structure):
@@ -95,7 +95,8 @@ class _DevView(ctypes.Structure):
                 ("ymc_pool_cells", ctypes.c_uint64), ("ymc_ctr", ctypes.c_void_p),
                 ("ymc_handles", ctypes.c_void_p), ("patience_enq", ctypes.c_uint32),
                 ("patience_deq", ctypes.c_uint32), ("help_delay", ctypes.c_uint32),
-                ("group_lanes", ctypes.c_uint32), ("help_ctr", ctypes.c_void_p)]
+                ("group_lanes", ctypes.c_uint32), ("help_ctr", ctypes.c_void_p),
+                ("ymc_hint", ctypes.c_void_p)]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -119,7 +120,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gq_read_stats": [P, P, P],
         "gq_clear_stats": [P, P],
         "gq_check_error": [P, P],
-        "gq_run_mix": [P, U64, U32, U32, P, P, P],
+        "gq_run_mix": [P, U64, U32, U32, P, P, P, P],
         "gq_run_balanced": [P, U32, U32, P, P, P],
         "gq_run_prodcons": [P, U64, U32, U32, P, U32, U64, U32, U32, U32, U64, U32, P, P, P],
         "gq_run_script": [P, U32, U32, P, P, P, P, U32, P, P],
@@ -221,6 +222,7 @@ class Stats:
     slow_enter: int
     helps: int
     scans: int
+    dropped: int
 
 
 class History:
@@ -328,11 +330,17 @@ class Queue:
 
     # ---- workload drivers --------------------------------------------------
     def run_mix(self, seed: int, lanes: int, ops_per_lane: int, counts, hist: History = None,
-                stream=None):
-        _need_words(counts, 4, "run_mix")
+                stream=None, lane_enq=None):
+        """Mixed 50/50 workload.  counts: 8 int64 words, added to: {ok_enq,
+        ok_deq, full, empty, S1_deq, S2_deq, S1_enq, S2_enq} (wrapping sums of
+        v and v*v).  lane_enq (optional int32[lanes]): each lane's count of
+        successful enqueues."""
+        _need_words(counts, 8, "run_mix")
         _need_hist(hist, lanes, "run_mix")
+        if lane_enq is not None and lane_enq.numel() * lane_enq.element_size() < 4 * lanes:
+            raise ValueError("run_mix: lane_enq needs one 32-bit word per lane")
         hc = hist.c() if hist is not None else None
-        _check(lib().gq_run_mix(self._h, seed, lanes, ops_per_lane, _ptr(counts),
+        _check(lib().gq_run_mix(self._h, seed, lanes, ops_per_lane, _ptr(counts), _ptr(lane_enq),
                                 ctypes.byref(hc) if hc is not None else None, _stream(stream)),
                "gq_run_mix")
 
@@ -427,7 +435,7 @@ class Multi:
         self._h = h
 
     def run_mix(self, seed: int, ops_per_lane: int, counts, hist: History = None, stream=None):
-        _need_words(counts, 4 * len(self.queues), "Multi.run_mix")
+        _need_words(counts, 8 * len(self.queues), "Multi.run_mix")
         _need_hist(hist, sum(self.lanes), "Multi.run_mix")
         hc = hist.c() if hist is not None else None
         _check(lib().gq_multi_run_mix(self._h, seed, ops_per_lane, _ptr(counts),
@@ -435,7 +443,7 @@ class Multi:
                                       _stream(stream)), "gq_multi_run_mix")
 
     def capture(self, seed: int, ops_per_lane: int, counts, stream):
-        _need_words(counts, 4 * len(self.queues), "Multi.capture")
+        _need_words(counts, 8 * len(self.queues), "Multi.capture")
         _check(lib().gq_multi_capture(self._h, seed, ops_per_lane, _ptr(counts), _stream(stream)),
                "gq_multi_capture")
 

@@ -143,7 +143,7 @@ def _mix_measure(kind, capacity, total_ops, reps):
         try:
             pre = torch.arange(1, capacity // 2 + 1, dtype=torch.int64, device="cuda")
             q.enqueue_batch(pre)
-            counts = torch.zeros(4, dtype=torch.int64, device="cuda")
+            counts = torch.zeros(8, dtype=torch.int64, device="cuda")
             seed = [0]
 
             def launch():
@@ -203,7 +203,7 @@ def _multi_measure(kind, caps, ops_factor, reps):
             for q, n in zip(qs, caps):
                 q.enqueue_batch(torch.arange(1, n // 2 + 1, dtype=torch.int64, device="cuda"))
             m = Multi(qs, lanes, block=256)
-            counts = torch.zeros(4 * len(qs), dtype=torch.int64, device="cuda")
+            counts = torch.zeros(8 * len(qs), dtype=torch.int64, device="cuda")
             seed = [0]
 
             def launch():
@@ -211,7 +211,7 @@ def _multi_measure(kind, caps, ops_factor, reps):
                 m.run_mix(seed[0], ops, counts)
 
             ms = _time_ms(torch, launch, reps)
-            cnt = counts.cpu().numpy().reshape(-1, 4)
+            cnt = counts.cpu().numpy().reshape(-1, 8)
             return ms, float(cnt[:, 0].sum() + cnt[:, 1].sum()) / (reps + 1)
         finally:
             if m is not None:

@@ -70,7 +70,7 @@ inline uint32_t ilog2(uint64_t x) {
 
 struct Layout {
   uint64_t slots_aq, slots_fq, data, rec_aq, rec_fq, own_aq, own_fq, help, hint, ymc_pool, ymc_handles,
-      total;
+      ymc_hint, total;
 };
 
 bool kind_supported(gq_kind kind) {
@@ -115,7 +115,8 @@ gq_status plan(gq_kind kind, uint64_t n, uint32_t w, uint32_t k, const gq_option
   off = align_up(off + slot_bytes, 4096);
   L->data = off;
   off = align_up(off + n * w, 4096);
-  L->rec_aq = L->rec_fq = L->own_aq = L->own_fq = L->help = L->hint = L->ymc_pool = L->ymc_handles = 0;
+  L->rec_aq = L->rec_fq = L->own_aq = L->own_fq = L->help = L->hint = L->ymc_pool = L->ymc_handles =
+      L->ymc_hint = 0;
   if (kind == GQ_WFQ) {
     L->rec_aq = off;
     off = align_up(off + (uint64_t)k * sizeof(wfq::Rec), 4096);
@@ -138,6 +139,8 @@ gq_status plan(gq_kind kind, uint64_t n, uint32_t w, uint32_t k, const gq_option
     off = align_up(off + cells * ymc::CELL_WORDS * 8, 4096);
     L->ymc_handles = off;
     off = align_up(off + (uint64_t)k * sizeof(ymc::Handle), 4096);
+    L->ymc_hint = off;
+    off = align_up(off + (uint64_t)k, 4096);
   }
   L->total = off;
   return GQ_OK;
@@ -241,6 +244,7 @@ __global__ void k_init_ymc(gq_dev q) {
     const uint32_t peer = (uint32_t)((t + 1) % q.max_threads);
     hd[t].enq_peer = peer;
     hd[t].deq_peer = peer;
+    q.ymc_hint[t] = 0;
   }
   if (g0 == 0) {
     st(q.ymc_ctr, 1ull);
@@ -374,10 +378,15 @@ struct Rec {
   }
 };
 
-// The end stamp is taken after an agent-scope release fence, so every write
-// of the operation is complete and visible before its recorded return.
-__device__ __forceinline__ uint64_t end_stamp() {
-  fence_rel();
+// The end stamp is taken once every memory access of the operation has
+// completed.  With the atomic hand-off every access that another lane reads
+// is a device-coherent atomic, visible once complete, so the lane only waits
+// for its outstanding accesses -- exactly what the unrecorded kernels'
+// operations do; the fenced hand-off's plain payload stores need an
+// agent-scope release before they are visible.
+__device__ __forceinline__ uint64_t end_stamp(const gq_dev& q) {
+  if (q.flags & GQ_OPT_FENCED) fence_rel();
+  else wait_mem();
   return stamp();
 }
 
@@ -385,40 +394,87 @@ __device__ __forceinline__ uint64_t end_stamp() {
 // One lane's part of the mixed workload on queue q: `ops` operations, op r an
 // enqueue iff the top bit of r(seed, (g << 32) | r) is 0, tried once.  g is
 // the lane's global id (tokens and draws), tid its id within the queue.
+// Per-lane tallies of the mixed workload: counts and the wrapping sums of v
+// and v * v of the items moved (the multiset checksums of gq_run_mix).  The
+// dequeued items' sums accumulate per operation; the enqueued items of lane g
+// are its tokens (g << 32) | j, j = 1..c, whose sums have a closed form in c:
+// with x = g << 32, sum = c x + c(c+1)/2 and sum of squares =
+// c x^2 + x c(c+1) + c(c+1)(2c+1)/6, both mod 2^64 (the divisions are exact
+// on the integers, so they are taken before the wrap).
+__device__ __forceinline__ void token_sums(uint64_t g, uint64_t c, uint64_t& s1, uint64_t& s2) {
+  const uint64_t x = g << 32;
+  const uint64_t tri = (c & 1) ? c * ((c + 1) >> 1) : (c >> 1) * (c + 1);  // c(c+1)/2
+  // c(c+1)(2c+1)/6 = tri * (2c+1) / 3: one of tri and 2c+1 is a multiple of 3
+  const uint64_t sq = (tri % 3 == 0) ? (tri / 3) * (2 * c + 1) : tri * ((2 * c + 1) / 3);
+  s1 = c * x + tri;
+  s2 = c * x * x + 2 * x * tri + sq;
+}
+
+struct MixTally {
+  uint32_t ok_e = 0, ok_d = 0, full = 0, empty = 0, cf = 0;
+  uint64_t s1d = 0, s2d = 0;
+  __device__ __forceinline__ void enq(int s, uint64_t) {
+    if (s == GQ_OK) ok_e++;
+    else full++;
+  }
+  __device__ __forceinline__ void deq(int s, uint64_t v) {
+    if (s == GQ_OK) {
+      ok_d++;
+      s1d += v;
+      s2d += v * v;
+    } else {
+      empty++;
+    }
+  }
+  // counts[0..7] += {ok_enq, ok_deq, full, empty, S1_deq, S2_deq, S1_enq, S2_enq}
+  // for lane g, whose tokens are (g << 32) | j
+  __device__ __forceinline__ void flush(uint64_t* counts, uint64_t* stats, uint64_t g) const {
+    uint64_t s1e, s2e;
+    token_sums(g, ok_e, s1e, s2e);
+    wave_add(counts + 0, ok_e);
+    wave_add(counts + 1, ok_d);
+    wave_add(counts + 2, full);
+    wave_add(counts + 3, empty);
+    wave_add(counts + 4, s1d);
+    wave_add(counts + 5, s2d);
+    wave_add(counts + 6, s1e);
+    wave_add(counts + 7, s2e);
+    wave_add(stats + S_CAS_FAIL, cf);
+  }
+};
+
 template <int KIND, bool REC>
 __device__ __forceinline__ void mix_lane(const gq_dev& q, uint64_t g, uint32_t tid, uint64_t seed,
-                                         uint32_t ops, uint64_t* counts, const Rec& rec) {
-  uint64_t seq = 0, ok_e = 0, ok_d = 0, full = 0, empty = 0;
-  uint32_t cf = 0;
+                                         uint32_t ops, uint64_t* counts, uint32_t* lane_enq,
+                                         const Rec& rec) {
+  MixTally t;
   for (uint32_t r = 0; r < ops; r++) {
     const bool is_enq = (splitmix64(seed, (g << 32) | r) >> 63) == 0;
     const uint64_t t0 = REC ? stamp() : 0;
     uint64_t v;
     int s;
     if (is_enq) {
-      v = (g << 32) | (seq + 1);
-      s = gq_enqueue_k<KIND>(q, v, tid, cf);
-      if (s == GQ_OK) { seq++; ok_e++; } else full++;
+      v = (g << 32) | (uint64_t)(t.ok_e + 1);
+      s = gq_enqueue_k<KIND>(q, v, tid, t.cf);
+      t.enq(s, v);
     } else {
       v = 0;
-      s = gq_dequeue_k<KIND>(q, &v, tid, cf);
-      if (s == GQ_OK) ok_d++; else { empty++; v = 0; }
+      s = gq_dequeue_k<KIND>(q, &v, tid, t.cf);
+      if (s != GQ_OK) v = 0;
+      t.deq(s, v);
     }
-    if (REC) rec.put(g, r, is_enq ? 0 : 1, s, v, t0, end_stamp());
+    if (REC) rec.put(g, r, is_enq ? 0 : 1, s, v, t0, end_stamp(q));
   }
   if (REC && rec.h.count) rec.h.count[g] = ops;
-  wave_add(counts + 0, ok_e);
-  wave_add(counts + 1, ok_d);
-  wave_add(counts + 2, full);
-  wave_add(counts + 3, empty);
-  wave_add(q.stats + S_CAS_FAIL, cf);
+  if (lane_enq) lane_enq[g] = t.ok_e;
+  t.flush(counts, q.stats, g);
 }
 
 template <int KIND, bool REC>
 __global__ __launch_bounds__(256) void k_mix(gq_dev q, uint64_t seed, uint32_t ops,
-                                             uint64_t* counts, Rec rec) {
+                                             uint64_t* counts, uint32_t* lane_enq, Rec rec) {
   const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  mix_lane<KIND, REC>(q, g, (uint32_t)g, seed, ops, counts, rec);
+  mix_lane<KIND, REC>(q, g, (uint32_t)g, seed, ops, counts, lane_enq, rec);
 }
 
 // The same workload with workgroup-aggregated first tickets: every lane of
@@ -427,38 +483,36 @@ __global__ __launch_bounds__(256) void k_mix(gq_dev q, uint64_t seed, uint32_t o
 // tokens and counts as k_mix.
 template <int KIND, bool REC>
 __device__ __forceinline__ void mix_group_body(const gq_dev& q, uint64_t seed, uint32_t ops,
-                                               uint64_t* counts, const Rec& rec, GroupLds& lds) {
+                                               uint64_t* counts, uint32_t* lane_enq,
+                                               const Rec& rec, GroupLds& lds) {
   uint32_t par = 0;
   const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   // per-lane counts never exceed `ops` (< 2^32): 32-bit registers suffice
-  uint32_t seq = 0, ok_e = 0, ok_d = 0, full = 0, empty = 0;
-  uint32_t cf = 0;
+  MixTally t;
   for (uint32_t r = 0; r < ops; r++) {
     const bool is_enq = (splitmix64(seed, (g << 32) | r) >> 63) == 0;
     const uint64_t t0 = REC ? stamp() : 0;
-    uint64_t v = is_enq ? ((g << 32) | (uint64_t)(seq + 1)) : 0;
-    const int s = gq_group_op_k<KIND>(q, is_enq ? ROLE_ENQ : ROLE_DEQ, v, (uint32_t)g, cf, lds,
+    uint64_t v = is_enq ? ((g << 32) | (uint64_t)(t.ok_e + 1)) : 0;
+    const int s = gq_group_op_k<KIND>(q, is_enq ? ROLE_ENQ : ROLE_DEQ, v, (uint32_t)g, t.cf, lds,
                                       par);
     if (is_enq) {
-      if (s == GQ_OK) { seq++; ok_e++; } else full++;
+      t.enq(s, v);
     } else {
-      if (s == GQ_OK) ok_d++; else { empty++; v = 0; }
+      if (s != GQ_OK) v = 0;
+      t.deq(s, v);
     }
-    if (REC) rec.put(g, r, is_enq ? 0 : 1, s, v, t0, end_stamp());
+    if (REC) rec.put(g, r, is_enq ? 0 : 1, s, v, t0, end_stamp(q));
   }
   if (REC && rec.h.count) rec.h.count[g] = ops;
-  wave_add(counts + 0, ok_e);
-  wave_add(counts + 1, ok_d);
-  wave_add(counts + 2, full);
-  wave_add(counts + 3, empty);
-  wave_add(q.stats + S_CAS_FAIL, cf);
+  if (lane_enq) lane_enq[g] = t.ok_e;
+  t.flush(counts, q.stats, g);
 }
 
 template <int KIND, bool REC>
 __global__ __launch_bounds__(1024) void k_mix_group(gq_dev q, uint64_t seed, uint32_t ops,
-                                                    uint64_t* counts, Rec rec) {
+                                                    uint64_t* counts, uint32_t* lane_enq, Rec rec) {
   __shared__ GroupLds lds;
-  mix_group_body<KIND, REC>(q, seed, ops, counts, rec, lds);
+  mix_group_body<KIND, REC>(q, seed, ops, counts, lane_enq, rec, lds);
 }
 
 // Many independent queues in one launch: wavefront w works on queue
@@ -472,7 +526,7 @@ __global__ __launch_bounds__(256) void k_multi_mix(const gq_dev* qs, const uint3
   const uint32_t qi = __builtin_amdgcn_readfirstlane(wave_q[g / 64]);
   const gq_dev q = qs[qi];
   const uint32_t tid = (uint32_t)(g - q_lane0[qi]);
-  mix_lane<KIND, REC>(q, g, tid, ld(seed), ops, counts + 4 * (uint64_t)qi, rec);
+  mix_lane<KIND, REC>(q, g, tid, ld(seed), ops, counts + 8 * (uint64_t)qi, nullptr, rec);
 }
 
 __global__ void k_seed(uint64_t* seed, uint64_t value, uint32_t bump) {
@@ -491,13 +545,13 @@ __global__ __launch_bounds__(256) void k_balanced(gq_dev q, uint32_t rounds, uin
     uint64_t v = (g << 32) | (seq + 1);
     int s = gq_enqueue_k<KIND>(q, v, (uint32_t)g, cf);
     if (s == GQ_OK) { seq++; ok_e++; } else full++;
-    if (REC) rec.put(g, r, 0, s, v, t0, end_stamp());
+    if (REC) rec.put(g, r, 0, s, v, t0, end_stamp(q));
     r++;
     t0 = REC ? stamp() : 0;
     v = 0;
     s = gq_dequeue_k<KIND>(q, &v, (uint32_t)g, cf);
     if (s == GQ_OK) ok_d++; else { empty++; v = 0; }
-    if (REC) rec.put(g, r, 1, s, v, t0, end_stamp());
+    if (REC) rec.put(g, r, 1, s, v, t0, end_stamp(q));
     r++;
   }
   if (REC && rec.h.count) rec.h.count[g] = r;
@@ -519,7 +573,6 @@ __global__ void k_prodcons(gq_dev q, uint64_t seed, const uint8_t* role, uint32_
   uint64_t seq = 0, ok_e = 0, ok_d = 0, full = 0, empty = 0;
   uint64_t s1d = 0, s2d = 0, s1e = 0, s2e = 0;
   uint32_t cf = 0, r = 0;
-  bool failed_last = false;  // the lane's previous operation answered FULL / EMPTY
   const uint64_t t_start = limit_ticks ? stamp() : 0;
   for (uint64_t k = 0;; k++) {
     if (producer ? seq >= quota : ld(taken) >= target) break;
@@ -543,8 +596,7 @@ __global__ void k_prodcons(gq_dev q, uint64_t seed, const uint8_t* role, uint32_
       } else {
         full++;
       }
-      if (REC && !(s != GQ_OK && failed_last)) rec.put(g, r++, 0, s, v, t0, end_stamp());
-      failed_last = s != GQ_OK;
+      if (REC) rec.put(g, r++, 0, s, v, t0, end_stamp(q));
     } else {
       uint64_t v = 0;
       const int s = gq_dequeue_k<KIND>(q, &v, (uint32_t)g, cf);
@@ -557,8 +609,7 @@ __global__ void k_prodcons(gq_dev q, uint64_t seed, const uint8_t* role, uint32_
         empty++;
         v = 0;
       }
-      if (REC && !(s != GQ_OK && failed_last)) rec.put(g, r++, 1, s, v, t0, end_stamp());
-      failed_last = s != GQ_OK;
+      if (REC) rec.put(g, r++, 1, s, v, t0, end_stamp(q));
     }
   }
   if (REC && rec.h.count) rec.h.count[g] = r;
@@ -645,7 +696,7 @@ __global__ void k_script(gq_dev q, uint32_t lanes, uint32_t spread, const uint8_
       s = gq_dequeue_k<KIND>(q, &v, g, cf);
       if (s != GQ_OK) v = 0;
     }
-    rec.put(g, r, ops[i], s, v, t0, end_stamp());
+    rec.put(g, r, ops[i], s, v, t0, end_stamp(q));
   }
   if (rec.h.count) rec.h.count[g] = n_ops[g];
 }
@@ -858,6 +909,7 @@ static gq_dev make_dev(gq_kind kind, uint64_t capacity, uint32_t item_width,
     d.ymc_cells = (uint64_t*)(buf + L.ymc_pool);
     d.ymc_pool_cells = (o.ymc_pool_cells ? o.ymc_pool_cells : ymc_default_cells(capacity));
     d.ymc_handles = buf + L.ymc_handles;
+    d.ymc_hint = (uint8_t*)(buf + L.ymc_hint);
     d.patience_enq = 10;  // the original algorithm's PATIENCE
     d.patience_deq = 10;
     if (o.flags & GQ_OPT_WFQ_TUNING) {
@@ -994,6 +1046,7 @@ gq_status gq_read_stats(gq_queue* q, gq_stats* out, void* stream) {
   out->slow_enter = s[S_SLOW];
   out->helps = s[S_HELPS];
   out->scans = s[S_SCAN];
+  out->dropped = s[S_DROP];
   return GQ_OK;
 }
 
@@ -1023,6 +1076,15 @@ static Rec make_rec(const gq_history* h) {
   return r;
 }
 
+static gq_status resident_blocks_of(const void* fn, uint32_t block, uint32_t* out) {
+  int dev = 0, cus = 0, nb = 0;
+  HIP_OK(hipGetDevice(&dev));
+  HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, (int)block, 0));
+  *out = (uint32_t)(nb * cus);
+  return GQ_OK;
+}
+
 // Each driver is instantiated per queue kind; KIND_SWITCH picks the
 // instantiation for q->kind.
 #define KIND_SWITCH(kind, CALL)                      \
@@ -1041,28 +1103,58 @@ static uint32_t group_block(const gq_queue* q, uint64_t lanes) {
   return b;
 }
 
+// The mixed workload's launch shape: workgroups of `block` lanes running the
+// group-ticket kernel (block > 64), or the per-wavefront kernel in workgroups
+// of `block` (256 or 64).  *fn receives the kernel.
 template <int KIND>
-static void launch_mix(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t ops, uint64_t* counts,
-                       const gq_history* hist, hipStream_t s) {
-  const Rec rec = make_rec(hist);
+static uint32_t mix_shape(const gq_queue* q, uint32_t lanes, bool hist, const void** fn) {
   const uint32_t gb = group_block(q, lanes);
   if (gb > 64) {
-    const dim3 grid(lanes / gb), block(gb);
-    if (hist) LAUNCH((k_mix_group<KIND, true>), grid, block, 0, s, q->dev, seed, ops, counts, rec);
-    else LAUNCH((k_mix_group<KIND, false>), grid, block, 0, s, q->dev, seed, ops, counts, rec);
+    *fn = hist ? (const void*)k_mix_group<KIND, true> : (const void*)k_mix_group<KIND, false>;
+    return gb;
+  }
+  *fn = hist ? (const void*)k_mix<KIND, true> : (const void*)k_mix<KIND, false>;
+  return lanes % kBlock == 0 ? kBlock : 64;
+}
+
+template <int KIND>
+static void launch_mix(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t ops, uint64_t* counts,
+                       uint32_t* lane_enq, const gq_history* hist, hipStream_t s) {
+  const Rec rec = make_rec(hist);
+  const void* fn = nullptr;
+  const uint32_t b = mix_shape<KIND>(q, lanes, hist != nullptr, &fn);
+  const dim3 grid(lanes / b), block(b);
+  if (fn == (const void*)k_mix_group<KIND, true> || fn == (const void*)k_mix_group<KIND, false>) {
+    if (hist)
+      LAUNCH((k_mix_group<KIND, true>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
+    else
+      LAUNCH((k_mix_group<KIND, false>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
     return;
   }
-  const uint32_t b = lanes % kBlock == 0 ? kBlock : 64;
-  const dim3 grid(lanes / b), block(b);
-  if (hist) LAUNCH((k_mix<KIND, true>), grid, block, 0, s, q->dev, seed, ops, counts, rec);
-  else LAUNCH((k_mix<KIND, false>), grid, block, 0, s, q->dev, seed, ops, counts, rec);
+  if (hist) LAUNCH((k_mix<KIND, true>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
+  else LAUNCH((k_mix<KIND, false>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
 }
 
 gq_status gq_run_mix(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t ops_per_lane,
-                     uint64_t* d_counts, const gq_history* hist, void* stream) {
+                     uint64_t* d_counts, uint32_t* d_lane_enq, const gq_history* hist,
+                     void* stream) {
   if (!q || !d_counts || lanes == 0 || lanes % 64 || lanes > q->k) return GQ_ERR_INVALID;
   if (hist && (!hist->val || !hist->call || !hist->ret || !hist->opst)) return GQ_ERR_INVALID;
-  KIND_SWITCH(q->kind, launch_mix<K>(q, seed, lanes, ops_per_lane, d_counts, hist, S(stream)));
+  // G-WFQ-YMC: every operation takes at least one cell; a run that could
+  // need more cells than the pool holds is refused up front.
+  if (q->kind == GQ_WFQ_YMC && (uint64_t)lanes * ops_per_lane > q->dev.ymc_pool_cells)
+    return GQ_ERR_POOL_EXHAUSTED;
+  if (q->kind == GQ_WFQ) {
+    // G-WFQ's wait-freedom holds for co-resident lanes (Section III-C)
+    const void* fn = nullptr;
+    const uint32_t b = mix_shape<GQ_WFQ>(q, lanes, hist != nullptr, &fn);
+    uint32_t resident = 0;
+    const gq_status st = resident_blocks_of(fn, b, &resident);
+    if (st != GQ_OK) return st;
+    if (lanes / b > resident) return GQ_ERR_RESIDENCY;
+  }
+  KIND_SWITCH(q->kind, launch_mix<K>(q, seed, lanes, ops_per_lane, d_counts, d_lane_enq, hist,
+                                     S(stream)));
   HIP_OK(hipGetLastError());
   return GQ_OK;
 }
@@ -1085,14 +1177,6 @@ gq_status gq_run_balanced(gq_queue* q, uint32_t lanes, uint32_t rounds, uint64_t
   return GQ_OK;
 }
 
-static gq_status resident_blocks_of(const void* fn, uint32_t block, uint32_t* out) {
-  int dev = 0, cus = 0, nb = 0;
-  HIP_OK(hipGetDevice(&dev));
-  HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, (int)block, 0));
-  *out = (uint32_t)(nb * cus);
-  return GQ_OK;
-}
 
 template <int KIND>
 static const void* prodcons_fn(bool hist) {
@@ -1235,6 +1319,7 @@ gq_status gq_probe_fence(uint64_t* d_lines, uint32_t lanes, uint32_t iters, uint
 template <int KIND>
 static const void* driver_fn(const char* kernel) {
   if (!strcmp(kernel, "mix")) return (const void*)k_mix<KIND, false>;
+  if (!strcmp(kernel, "mix_group")) return (const void*)k_mix_group<KIND, false>;
   if (!strcmp(kernel, "prodcons")) return (const void*)k_prodcons<KIND, false>;
   return nullptr;
 }

@@ -73,7 +73,7 @@ def test_null_arguments_rejected():
     assert L.gq_destroy(None) == b.GQ_ERR_INVALID
     assert L.gq_create(0, 1024, 8, 1, None, None, 0, None) == b.GQ_ERR_INVALID
     assert L.gq_enqueue_batch(None, None, 0, None, None, None) == b.GQ_ERR_INVALID
-    assert L.gq_run_mix(None, 0, 256, 1, None, None, None) == b.GQ_ERR_INVALID
+    assert L.gq_run_mix(None, 0, 256, 1, None, None, None, None) == b.GQ_ERR_INVALID
 
 
 def test_wfq_cycle_bound_refused_at_create():

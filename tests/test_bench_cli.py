@@ -23,3 +23,33 @@ def test_help_lists_the_section_switches():
     for flag in ("--no-c2", "--no-timed", "--no-c3", "--no-serve", "--no-rt", "--no-bfs",
                  "--no-multi", "--no-cpu"):
         assert flag in r.stdout
+
+
+def test_step_plan_does_not_grow_with_steps():
+    """The driver's --steps 20 --warmup 5 (and any longer run) fits: every step
+    starts from a reset queue, so G-WFQ-YMC's pool holds one step's cells."""
+    sys.path.insert(0, ROOT)
+    import bench
+    for steps, warmup in ((20, 5), (5, 2), (1000, 100)):
+        p = bench.step_plan(steps, warmup)
+        assert p["reset_each_step"] and p["fits"]
+        assert p["launches"] == steps + warmup
+        assert p["ymc_cells_needed_per_step"] == bench.LANES * bench.OPS_PER_LANE + bench.CAP // 2
+        assert p["ymc_cells_needed_per_step"] <= p["ymc_pool_cells"]
+
+
+def test_checksums_of_a_split_multiset_add_up():
+    """The bench's per-step conservation check: checksums of a union are the
+    wrapping sums of the parts' checksums."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+
+    import bench
+    rng = np.random.default_rng(3)
+    v = rng.integers(0, 2**64, size=1000, dtype=np.uint64)
+    a, b = v[:377], v[377:]
+    assert bench.csum_add(bench.checksums(a), bench.checksums(b)) == bench.checksums(v)
+    # a lost item and a duplicated one change the sums
+    w = v.copy()
+    w[5] = w[6]
+    assert bench.checksums(w) != bench.checksums(v)

@@ -32,7 +32,7 @@ def test_multi_queue_histories(kind):
     print(f"[case] kind={kind} caps={caps} lanes={lanes}", flush=True)
     m = gq.Multi(qs, lanes, block=256)
     ops = 16
-    counts = T.zeros(4 * len(qs), dtype=T.int64, device="cuda")
+    counts = T.zeros(8 * len(qs), dtype=T.int64, device="cuda")
     total = sum(lanes)
     h = gq.History(total, ops)
     seed = workloads.run_seed(5, 0)
@@ -42,7 +42,7 @@ def test_multi_queue_histories(kind):
     assert overflow == 0
     # the device drew each lane's roles from the shared workload definition
     assert np.array_equal(op, workloads.mix_roles(seed, total, ops).ravel())
-    c = counts.cpu().numpy().reshape(-1, 4)
+    c = counts.cpu().numpy().reshape(-1, 8)
     lane0 = np.concatenate([[0], np.cumsum(lanes)])
     for i, q in enumerate(qs):
         assert q.check_error() == gq.GQ_OK, i
@@ -69,17 +69,17 @@ def test_multi_queue_graph_replays(kind):
     qs = [gq.Queue(kind, c, item_width=8, max_threads=l) for c, l in zip(caps, lanes)]
     m = gq.Multi(qs, lanes, block=256)
     s = T.cuda.Stream()
-    counts = T.zeros(4 * len(qs), dtype=T.int64, device="cuda")
+    counts = T.zeros(8 * len(qs), dtype=T.int64, device="cuda")
     with T.cuda.stream(s):
         m.capture(workloads.run_seed(5, 1), 8, counts, s)
     s.synchronize()
     size = np.zeros(len(qs), dtype=np.int64)
-    prev = np.zeros((len(qs), 4), dtype=np.int64)
+    prev = np.zeros((len(qs), 8), dtype=np.int64)
     for rep in range(4):
         with T.cuda.stream(s):
             m.replay(s)
         s.synchronize()
-        c = counts.cpu().numpy().reshape(-1, 4)
+        c = counts.cpu().numpy().reshape(-1, 8)
         d = c - prev
         prev = c.copy()
         assert (d[:, 0] + d[:, 1] + d[:, 2] + d[:, 3] == np.array(lanes) * 8).all(), rep

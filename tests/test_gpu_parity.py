@@ -189,7 +189,7 @@ def test_c1_role_split(kind, run):
     prod_waves = workloads.producer_waves(seed, 16, 8)
     role = np.repeat(np.where(prod_waves, 0, 1), 64).astype(np.uint8)
     counts = T.zeros(8, dtype=T.int64, device="cuda")
-    h = gq.History(lanes, 1 << 14)
+    h = gq.History(lanes, 1 << 15)  # every poll is recorded
     q.run_prodcons(seed, lanes, block, T.tensor(role, device="cuda"), 64, 32768, 0, 1, counts, h,
                    max_rounds=1 << 22)
     T.cuda.synchronize()
@@ -292,7 +292,7 @@ def run_mix_checked(kind, n, lanes, ops, seed, slot_mode="linear", do_prefill=Tr
     if do_prefill:
         pre = [int(workloads.token(0xFFFFFFFF, i)) for i in range(n // 2)]
         prefill(q, pre)
-    counts = T.zeros(4, dtype=T.int64, device="cuda")
+    counts = T.zeros(8, dtype=T.int64, device="cuda")
     h = gq.History(lanes, ops)
     q.run_mix(seed, lanes, ops, counts, h)
     T.cuda.synchronize()
@@ -302,8 +302,11 @@ def run_mix_checked(kind, n, lanes, ops, seed, slot_mode="linear", do_prefill=Tr
     # the device drew the same roles as the shared workload definition
     roles = workloads.mix_roles(seed, lanes, ops).ravel()
     assert np.array_equal(hist.op, roles)
-    c = counts.cpu().tolist()
+    c = counts.cpu().numpy().view(np.uint64).tolist()
     assert c[0] == int(((hist.op == 0) & (hist.st == 0)).sum())
+    # the kernel's multiset checksums equal the oracle's over the recorded items
+    assert (c[1], c[4], c[5]) == oracle.multiset_checksums(hist.deq_ok())
+    assert (c[0], c[6], c[7]) == oracle.multiset_checksums(hist.enq_ok())
     expect = len(pre) + c[0] - c[1]
     drain = drain_fifo(q, n if BOUNDED[kind] else expect + 1)
     assert len(drain) == expect
@@ -341,6 +344,55 @@ def test_mix_history_fenced_handoff(kind, n):
     """The release/acquire payload hand-off (GQ_OPT_FENCED) passes the same checks."""
     lanes = 1024 if n < 64 else 16384  # G-WFQ's cycle bound at tiny capacity
     run_mix_checked(kind, n, lanes, 32, workloads.run_seed(2, 78), fenced=True)
+
+
+def checksum_add(a, b):
+    """Checksums (count, S1, S2) of the union of two multisets."""
+    m = (1 << 64) - 1
+    return a[0] + b[0], (a[1] + b[1]) & m, (a[2] + b[2]) & m
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("tg", TICKET_GROUPS)
+def test_mix_timed_kernel_conserves(kind, tg):
+    """The kernel the benchmark times, in the benchmark's own launch: no
+    history, atomic hand-off, capacity 2^20, 2048 x 256 lanes x 128 ops (2^26),
+    prefill n/2.  O3 conservation at full size: the tokens the lanes enqueued
+    (from their per-lane enqueue counts) and the prefill must equal, as a
+    multiset, what the lanes dequeued plus what a sequential drain finds left
+    (checksums: count and wrapping sums of v and v*v); the kernel's own
+    enqueue checksums must equal the oracle's over those tokens; the drained
+    residual must consist of distinct generated tokens, each producer's in
+    increasing order (a FIFO's remainder)."""
+    import paper_2606_01693_amd as gq
+    T = torch()
+    n, lanes, ops = 1 << 20, 2048 * 256, 128
+    seed = workloads.run_seed(2, 1)
+    q = make_queue(kind, n, lanes=lanes, ticket_group=tg,
+                   **({"ymc_pool_cells": 1 << 27} if kind == "ymc" else {}))
+    pre = np.array([int(workloads.token(0xFFFFFFFF, i)) for i in range(n // 2)], dtype=np.uint64)
+    q.enqueue_batch(T.tensor(pre.view(np.int64), device="cuda"))
+    counts = T.zeros(8, dtype=T.int64, device="cuda")
+    lane_enq = T.zeros(lanes, dtype=T.int32, device="cuda")
+    q.run_mix(seed, lanes, ops, counts, lane_enq=lane_enq)
+    T.cuda.synchronize()
+    assert q.check_error() == gq.GQ_OK
+    assert q.stats().dropped == 0
+    c = counts.cpu().numpy().view(np.uint64).tolist()
+    enq = oracle.mix_tokens_from_counts(lane_enq.cpu().numpy())
+    assert oracle.multiset_checksums(enq) == (c[0], c[6], c[7])
+    assert c[0] + c[1] + c[2] + c[3] == lanes * ops
+    drain = drain_fifo(q, n if BOUNDED[kind] else len(pre) + c[0] - c[1] + 1)
+    assert len(drain) == len(pre) + c[0] - c[1]
+    put = checksum_add(oracle.multiset_checksums(pre), oracle.multiset_checksums(enq))
+    out = checksum_add((c[1], c[4], c[5]), oracle.multiset_checksums(drain))
+    assert put == out, (put, out)
+    assert len(np.unique(drain)) == len(drain)
+    rep = oracle.conservation(np.concatenate([pre, enq]), drain)
+    assert rep["extra"] == 0, rep
+    dh = oracle.History(np.zeros(len(drain)), np.ones(len(drain)), np.zeros(len(drain)), drain,
+                        2 * np.arange(len(drain)), 2 * np.arange(len(drain)) + 1)
+    assert oracle.producer_order(dh)["consumer_order"] == 0
 
 
 @pytest.mark.parametrize("kind", KINDS)
