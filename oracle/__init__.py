@@ -24,6 +24,7 @@ from .linearize import check_linearizable  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gq_oracle.c")
+_SRC_LIN = os.path.join(_HERE, "gq_linsearch.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OP_ENQ, OP_DEQ = 0, 1
@@ -33,7 +34,7 @@ ST_OK, ST_EMPTY, ST_FULL = 0, 1, 2
 def build() -> str:
     """Compile the oracle's C part with gcc (always rebuilds)."""
     cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-pthread",
-           _SRC, "-o", _LIB + ".tmp"]
+           _SRC, _SRC_LIN, "-o", _LIB + ".tmp"]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -60,6 +61,9 @@ def lib():
         L.orc_violation_scan.argtypes = [U64, P, P, P, P, P, U64, P, U64, P, U64, P]
         L.orc_bfs.restype = ctypes.c_int64
         L.orc_bfs.argtypes = [U64, P, P, ctypes.c_uint32, P, P]
+        L.orc_lin_witness.restype = ctypes.c_int
+        L.orc_lin_witness.argtypes = [U64, P, P, P, P, P, U64, P, U64, P, ctypes.c_int, U64, U64,
+                                      ctypes.c_uint32, P, P]
         L.orc_locked_queue_run.restype = ctypes.c_int
         L.orc_locked_queue_run.argtypes = [ctypes.c_uint32, U64, P, U64, U64, P,
                                            ctypes.POINTER(ctypes.c_double)]
@@ -216,6 +220,83 @@ def violation_scan(h: History, prefill=(), drain=(), capacity: int = 0):
     if rc != int(any(rep.values())):
         raise AssertionError(f"orc_violation_scan returned {rc} with counts {rep}")
     return rep
+
+
+# ----------------------------------------------------------------------------
+# O10 linearization witness search
+# ----------------------------------------------------------------------------
+LIN_FOUND, LIN_NONE, LIN_UNKNOWN, LIN_UNSUPPORTED = 1, 0, -1, -2
+
+
+def lin_witness(h: History, prefill=(), drain=(), drain_ends_empty: bool = True,
+                capacity: int = 0, budget: int = 1 << 62, width: int = 0):
+    """Search for a linearization of the history (Section IV).
+
+    Returns (code, order, info): code 1 = found (order: operation indices in
+    linearization order; len(h) + j is the j-th drained item's dequeue and
+    len(h) + len(drain) the drain's final EMPTY), 0 = none exists (complete
+    search: width 0 or no branch cut short), -1 = undecided within the budget
+    or width, -2 = unsupported history (an item enqueued twice, ...).
+    width 0 is the exhaustive, memoised search; width w > 0 keeps the w best
+    candidates per branch (for large histories); `budget` bounds the dead
+    ends (backtracks) before the search gives up."""
+    pre = _u64(prefill)
+    dr = _u64(drain)
+    m = len(h)
+    M = m + dr.shape[0] + (1 if drain_ends_empty else 0)
+    order = np.zeros(max(M, 1), dtype=np.uint64)
+    info = np.zeros(4, dtype=np.uint64)
+    rc = lib().orc_lin_witness(m, _p(h.op), _p(h.st), _p(h.val), _p(h.call), _p(h.ret),
+                               pre.shape[0], _p(pre), dr.shape[0], _p(dr),
+                               1 if drain_ends_empty else 0, capacity, budget, width,
+                               _p(order), _p(info))
+    if rc == -3:
+        raise MemoryError("orc_lin_witness")
+    return rc, (order[:M].astype(np.int64) if rc == 1 else None), {
+        "branches": int(info[0]), "backtracks": int(info[1]), "longest_prefix": int(info[2]),
+        "dead_end_op": int(info[3]) if int(info[3]) != (1 << 64) - 1 else -1}
+
+
+def check_witness(h: History, order, prefill=(), drain=(), drain_ends_empty: bool = True,
+                  capacity: int = 0) -> str:
+    """Independent check of a claimed linearization: it must be a permutation
+    of all operations (history, drained dequeues, final EMPTY), keep real-time
+    precedence (no operation placed after one that was called after it
+    returned), and replay through the sequential FIFO (O2) with every
+    answer reproduced; FULL answers are effect-free and are left out of the
+    replay.  Returns "" when it holds, else what failed."""
+    dr = _u64(drain)
+    m = len(h)
+    M = m + dr.shape[0] + (1 if drain_ends_empty else 0)
+    order = np.asarray(order, dtype=np.int64)
+    if order.shape[0] != M or not np.array_equal(np.sort(order), np.arange(M)):
+        return "not a permutation of the operations"
+    tmax = int(max(h.call.max(initial=0), h.ret.max(initial=0)))
+    extra = M - m
+    call = np.concatenate([h.call, np.array([tmax + 1 + 2 * j for j in range(extra)],
+                                            dtype=np.uint64)])
+    ret = np.concatenate([h.ret, np.array([tmax + 2 + 2 * j for j in range(extra)],
+                                          dtype=np.uint64)])
+    op = np.concatenate([h.op, np.full(extra, OP_DEQ, dtype=np.uint8)])
+    st = np.concatenate([h.st, np.array([ST_OK] * dr.shape[0] + [ST_EMPTY] * (extra - dr.shape[0]),
+                                        dtype=np.uint8)])
+    val = np.concatenate([h.val, dr, np.zeros(extra - dr.shape[0], dtype=np.uint64)])
+    # real time: the largest call placed so far must not exceed any later return
+    c = call[order]
+    r = ret[order]
+    before = np.maximum.accumulate(c)[:-1]  # largest call among the positions before k
+    if np.any(before > r[1:]):
+        k = int(np.argmax(before > r[1:])) + 1
+        return f"real-time order broken at position {k}"
+    keep = order[st[order] != ST_FULL]
+    rs, rv, _ = fifo_replay(op[keep], val[keep], capacity=capacity, prefill=prefill)
+    if not np.array_equal(rs, st[keep]):
+        k = int(np.argmax(rs != st[keep]))
+        return f"replay status differs at position {k}"
+    okd = (op[keep] == OP_DEQ) & (st[keep] == ST_OK)
+    if not np.array_equal(rv[okd], val[keep][okd]):
+        return "replay dequeue values differ"
+    return ""
 
 
 def all_zero(d: dict) -> bool:
