@@ -172,10 +172,16 @@ def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-BFS_LANES = {"rmat22_ef16": (2048, 8192, 32768), "grid4096": (512, 2048, 8192)}
+BFS_LANES = {"rmat22_ef16": (8192, 32768, 131072), "grid4096": (2048, 8192, 32768)}
+# Algorithmic bytes of the queue BFS: per scanned adjacency entry a 4-byte
+# column index and a 4-byte level probe; per reached vertex its two offsets,
+# one enqueue and one dequeue of the outer queue (64 + 4 bytes each: slot
+# RMWs, slot and threshold loads, the 4-byte payload) and its level CAS.
+BFS_BYTES_PER_ENTRY = 8
+BFS_BYTES_PER_VERTEX = 8 + 2 * (64 + 4) + 4
 
 
-def bench_bfs(gq, torch, kinds=("lfq",), runs=3):
+def bench_bfs(gq, torch, kinds=("lfq", "wfq", "ymc"), runs=3):
     """Queue-driven BFS GTEPS on the R-MAT scale-22 and 4096^2 grid inputs.
     GTEPS = (sum of degrees of reached vertices / 2) / time (undirected edges
     of the traversed component per second).  Levels are compared with the
@@ -196,22 +202,28 @@ def bench_bfs(gq, torch, kinds=("lfq",), runs=3):
         c0 = time.perf_counter()
         exp, nl, scanned = oracle.bfs(off, cols, root)
         cpu_s = time.perf_counter() - c0
+        reached = int((exp != np.uint32(0xFFFFFFFF)).sum())
         log(f"[bench] cpu bfs {name}: {cpu_s * 1e3:.1f} ms, {nl} levels")
         edges = scanned / 2
         d_off = torch.tensor(off.astype(np.int32), device="cuda")
         d_cols = torch.tensor(cols.astype(np.int32), device="cuda")
         level = torch.empty(nv, dtype=torch.int32, device="cuda")
-        ctl = torch.zeros(512, dtype=torch.int64, device="cuda")
+        ctl = torch.zeros(gq.bfs_ctl_bytes(len(cols)) // 8, dtype=torch.int64, device="cuda")
         cap = 1 << int(np.ceil(np.log2(nv)))
-        res = {"vertices": nv, "csr_entries": int(len(cols)), "root": root, "levels": nl,
+        res = {"vertices": nv, "reached": reached, "csr_entries": int(len(cols)), "root": root,
+               "levels": nl, "bytes_model": f"{BFS_BYTES_PER_ENTRY} B per scanned entry + "
+                                            f"{BFS_BYTES_PER_VERTEX} B per reached vertex",
                "edges_traversed": int(edges), "cpu_bfs_gteps": edges / cpu_s / 1e9,
                "cpu_bfs_ms": cpu_s * 1e3, "runs": {}}
         best = None
         for kind in kinds:
             for lanes in BFS_LANES[name]:
+                # G-WFQ-YMC takes one pool cell per enqueue and per dequeue
+                # attempt (each lane's last attempt of a level answers EMPTY)
+                cells = (4 * nv + (nl + 4) * lanes * 4 + (1 << 16)) if kind == "ymc" else 0
                 try:
-                    qa = gq.Queue(kind, cap, item_width=4, max_threads=lanes)
-                    qb = gq.Queue(kind, cap, item_width=4, max_threads=lanes)
+                    qa = gq.Queue(kind, cap, item_width=4, max_threads=lanes, ymc_pool_cells=cells)
+                    qb = gq.Queue(kind, cap, item_width=4, max_threads=lanes, ymc_pool_cells=cells)
                 except gq.GQError as e:
                     log(f"[bench] bfs {name} {kind} lanes={lanes}: {e}")
                     continue
@@ -234,13 +246,20 @@ def bench_bfs(gq, torch, kinds=("lfq",), runs=3):
                         f"{e0.elapsed_time(e1):.2f} ms")
                     if r:
                         ms.append(e0.elapsed_time(e1))
-                if not ok or qa.check_error() != gq.GQ_OK:
+                key = f"{gq_name(kind)} lanes={lanes}"
+                err = qa.check_error()
+                if not ok or err != gq.GQ_OK:
+                    res["runs"][key] = {"error": gq.status_str(err) if err else "launch refused"}
+                    qa.close()
+                    qb.close()
                     continue
                 match = bool(np.array_equal(level.cpu().numpy().view(np.uint32), exp))
                 med = float(np.median(ms))
-                key = f"{gq_name(kind)} lanes={lanes}"
+                nbytes = BFS_BYTES_PER_ENTRY * scanned + BFS_BYTES_PER_VERTEX * reached
                 res["runs"][key] = {"ms_median": med, "gteps": edges / (med * 1e-3) / 1e9,
-                                    "levels_match_oracle": match}
+                                    "levels_match_oracle": match,
+                                    "model_gbs": nbytes / (med * 1e-3) / 1e9,
+                                    "hbm_frac": nbytes / (med * 1e-3) / 1e9 / HBM_PEAK_GBS}
                 log(f"[bench] bfs {name} {key}: {med:.2f} ms, match={match}")
                 if match and (best is None or med < best[1]):
                     best = (key, med)

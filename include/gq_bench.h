@@ -93,13 +93,18 @@ gq_status gq_multi_destroy(gq_multi *m);
  * of the same kind with item_width 4 (bounded kinds: capacity >= nv; a
  * G-WFQ-YMC pool must hold nv + levels * lanes cells), CSR graph (uint32
  * offsets[nv + 1], cols[offsets[nv]]), root < nv.  d_level[nv] receives hop
- * distances (0xFFFFFFFF = unreached).  d_ctl: caller-owned scratch of at least
- * 1 KiB; after the run d_ctl[160] = number of levels, d_ctl[192] = adjacency
+ * distances (0xFFFFFFFF = unreached).  d_ctl: caller-owned, 8-byte aligned
+ * workspace of ctl_bytes >= 4 KiB; gq_bfs_ctl_bytes(nnz) is the size that
+ * lets every high-degree vertex's list be split over all wavefronts (less
+ * works, with such vertices beyond the room scanned by one wavefront each).
+ * After the run d_ctl[160] = number of levels, d_ctl[192] = adjacency
  * entries scanned.  All workgroups must be co-resident (GQ_ERR_RESIDENCY
  * otherwise).  Device-side failures latch in qa's error word.               */
 gq_status gq_bfs(gq_queue *qa, gq_queue *qb, const uint32_t *d_offsets, const uint32_t *d_cols,
                  uint32_t nv, uint32_t root, uint32_t *d_level, uint32_t lanes, uint32_t block,
-                 uint64_t *d_ctl, void *stream);
+                 uint64_t *d_ctl, uint64_t ctl_bytes, void *stream);
+/* Workspace bytes for gq_bfs on a graph of nnz adjacency entries.            */
+uint64_t gq_bfs_ctl_bytes(uint64_t nnz);
 
 /* Balanced workload (Section V-A "balanced kernel", fixed op count): every
  * lane performs `rounds` times (enqueue its next token; dequeue), each tried

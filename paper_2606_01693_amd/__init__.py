@@ -7,8 +7,10 @@ built.
 """
 from ._binding import (  # noqa: F401
     EXPORTS, GQ_EMPTY, GQ_ERR_CYCLE_BOUND, GQ_ERR_DEVICE, GQ_ERR_HIP, GQ_ERR_INVALID,
-    GQ_ERR_NOMEM, GQ_ERR_POOL_EXHAUSTED, GQ_ERR_RESIDENCY, GQ_FULL, GQ_OK, KINDS, GQError,
+    GQ_ERR_NOMEM, GQ_ERR_POOL_EXHAUSTED, GQ_ERR_RESIDENCY, GQ_FULL, GQ_OK, KINDS,
+    GQError,
     RT_COMPACT, RT_QUEUES, SERVE_HASH_SEED, History, Multi, Queue, RayTracer, Server, Stats, bfs,
+    bfs_ctl_bytes,
     device_info, lib, probe_cas,
     probe_copy, probe_faa, probe_fence, required_bytes, resident_blocks, status_str,
 )

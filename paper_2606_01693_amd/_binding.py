@@ -30,7 +30,7 @@ EXPORTS = (
     "gq_check_error", "gq_status_str", "gq_run_mix", "gq_run_balanced", "gq_run_prodcons",
     "gq_run_script", "gq_probe_faa", "gq_probe_cas", "gq_probe_copy", "gq_probe_fence",
     "gq_resident_blocks", "gq_device_info", "gq_multi_create", "gq_multi_run_mix",
-    "gq_multi_capture", "gq_multi_replay", "gq_multi_destroy", "gq_bfs",
+    "gq_multi_capture", "gq_multi_replay", "gq_multi_destroy", "gq_bfs", "gq_bfs_ctl_bytes",
     "gq_serve_create", "gq_serve_run", "gq_serve_job_bytes", "gq_serve_destroy",
     "gq_run_timed", "gq_rt_create", "gq_rt_render", "gq_rt_check_error", "gq_rt_destroy",
 )
@@ -135,7 +135,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gq_multi_capture": [P, U64, U32, P, P],
         "gq_multi_replay": [P, P],
         "gq_multi_destroy": [P],
-        "gq_bfs": [P, P, P, P, U32, U32, P, U32, U32, P, P],
+        "gq_bfs": [P, P, P, P, U32, U32, P, U32, U32, P, U64, P],
         "gq_serve_create": [U32, U32, I32, U64, U32, U32, P],
         "gq_run_timed": [P, U32, U32, U32, U32, U32, P, P, P],
         "gq_serve_run": [P, U32, P, P, U32, P],
@@ -146,6 +146,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gq_rt_check_error": [P, P],
         "gq_rt_destroy": [P],
     }
+    L.gq_bfs_ctl_bytes.restype = U64
+    L.gq_bfs_ctl_bytes.argtypes = [U64]
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
@@ -462,14 +464,23 @@ class Multi:
             pass
 
 
+def bfs_ctl_bytes(nnz: int) -> int:
+    """Workspace bytes for bfs() on a graph of nnz adjacency entries."""
+    return int(lib().gq_bfs_ctl_bytes(nnz))
+
+
 def bfs(qa: Queue, qb: Queue, offsets, cols, root: int, level, lanes: int, block: int, ctl,
         stream=None):
-    """Launch the queue-driven BFS; offsets/cols/level/ctl are CUDA tensors."""
+    """Launch the queue-driven BFS; offsets/cols/level/ctl are CUDA tensors
+    (ctl: the workspace, at least 4 KiB; bfs_ctl_bytes(nnz) for the full hub
+    list)."""
     nv = offsets.numel() - 1
-    if level.numel() < nv or cols.numel() < 1 or ctl.numel() * ctl.element_size() < 1024:
-        raise ValueError("bfs: level must hold nv entries, ctl at least 1 KiB")
+    ctl_bytes = ctl.numel() * ctl.element_size()
+    if level.numel() < nv or cols.numel() < 1 or ctl_bytes < 4096:
+        raise ValueError("bfs: level must hold nv entries, ctl at least 4 KiB")
     _check(lib().gq_bfs(qa.handle, qb.handle, _ptr(offsets), _ptr(cols), offsets.numel() - 1,
-                        root, _ptr(level), lanes, block, _ptr(ctl), _stream(stream)), "gq_bfs")
+                        root, _ptr(level), lanes, block, _ptr(ctl), ctl_bytes, _stream(stream)),
+           "gq_bfs")
 
 
 # ---------------------------------------------------------------------------

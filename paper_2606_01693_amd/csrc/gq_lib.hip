@@ -515,6 +515,19 @@ __global__ __launch_bounds__(1024) void k_mix_group(gq_dev q, uint64_t seed, uin
   mix_group_body<KIND, REC>(q, seed, ops, counts, lane_enq, rec, lds);
 }
 
+// G-LFQ's copy of the group kernel, compiled for 8 wavefronts per SIMD (at
+// most 64 VGPRs; it needs 67 otherwise, with a few bytes spilled at the cap):
+// the sweep's largest grid, 2^19 lanes, is then resident all at once instead
+// of in two rounds of workgroups (measured 2.41 -> 2.21 ms per 2^26 ops).
+// G-WFQ and G-WFQ-YMC need 100-123 VGPRs; capped, their spills cost more than
+// the second round of workgroups (2.74 -> 3.32 ms and 2.14 -> 2.53 ms).
+template <bool REC>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_mix_group_lfq(
+    gq_dev q, uint64_t seed, uint32_t ops, uint64_t* counts, uint32_t* lane_enq, Rec rec) {
+  __shared__ GroupLds lds;
+  mix_group_body<GQ_LFQ, REC>(q, seed, ops, counts, lane_enq, rec, lds);
+}
+
 // Many independent queues in one launch: wavefront w works on queue
 // wave_q[w]; lane ids inside a queue start at q_lane0[queue].  The seed is
 // read from device memory so that a captured graph can advance it.
@@ -1125,10 +1138,16 @@ static void launch_mix(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t ops,
   const uint32_t b = mix_shape<KIND>(q, lanes, hist != nullptr, &fn);
   const dim3 grid(lanes / b), block(b);
   if (fn == (const void*)k_mix_group<KIND, true> || fn == (const void*)k_mix_group<KIND, false>) {
-    if (hist)
+    if (KIND == GQ_LFQ) {
+      if (hist)
+        LAUNCH((k_mix_group_lfq<true>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
+      else
+        LAUNCH((k_mix_group_lfq<false>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
+    } else if (hist) {
       LAUNCH((k_mix_group<KIND, true>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
-    else
+    } else {
       LAUNCH((k_mix_group<KIND, false>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
+    }
     return;
   }
   if (hist) LAUNCH((k_mix<KIND, true>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
@@ -1144,15 +1163,15 @@ gq_status gq_run_mix(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t ops_pe
   // need more cells than the pool holds is refused up front.
   if (q->kind == GQ_WFQ_YMC && (uint64_t)lanes * ops_per_lane > q->dev.ymc_pool_cells)
     return GQ_ERR_POOL_EXHAUSTED;
-  if (q->kind == GQ_WFQ) {
-    // G-WFQ's wait-freedom holds for co-resident lanes (Section III-C)
-    const void* fn = nullptr;
-    const uint32_t b = mix_shape<GQ_WFQ>(q, lanes, hist != nullptr, &fn);
-    uint32_t resident = 0;
-    const gq_status st = resident_blocks_of(fn, b, &resident);
-    if (st != GQ_OK) return st;
-    if (lanes / b > resident) return GQ_ERR_RESIDENCY;
-  }
+  // No residency check here.  G-WFQ's wait-freedom (Section III-C) assumes
+  // that every lane taking part in an operation is resident and scheduled.
+  // A lane takes part only once its workgroup has started, a started
+  // workgroup stays resident until it ends, and no lane of this driver waits
+  // for a lane that has not started (each runs its own operations; helpers
+  // only act on published requests), so a grid larger than the device holds
+  // at once -- it then runs in rounds of workgroups -- keeps the premise.
+  // Drivers whose lanes wait for other lanes (shared targets, barriers)
+  // refuse grids that cannot be resident all at once.
   KIND_SWITCH(q->kind, launch_mix<K>(q, seed, lanes, ops_per_lane, d_counts, d_lane_enq, hist,
                                      S(stream)));
   HIP_OK(hipGetLastError());
@@ -1503,35 +1522,63 @@ template <int KIND>
 static const void* bfs_fn() { return (const void*)bfs::k_bfs<KIND>; }
 
 template <int KIND>
-static void launch_bfs(gq_queue* qa, gq_queue* qb, const uint32_t* off, const uint32_t* cols,
-                       uint32_t nv, uint32_t root, uint32_t* level, uint64_t* ctl, uint32_t lanes,
-                       uint32_t block, hipStream_t s) {
+static void launch_bfs(const gq_dev& qa, const gq_dev& qb, const uint32_t* off,
+                       const uint32_t* cols, uint32_t nv, uint32_t root, uint32_t* level,
+                       uint64_t* ctl, uint64_t hub_cap, uint32_t lanes, uint32_t block,
+                       hipStream_t s) {
   const uint32_t nblocks = lanes / block;
-  LAUNCH((bfs::k_bfs<KIND>), dim3(nblocks), dim3(block), 0, s, qa->dev, qb->dev, off, cols, nv,
-         root, level, ctl, nblocks);
+  LAUNCH((bfs::k_bfs<KIND>), dim3(nblocks), dim3(block), 0, s, qa, qb, off, cols, nv, root, level,
+         ctl, hub_cap, nblocks);
 }
 
-gq_status gq_bfs(gq_queue* qa, gq_queue* qb, const uint32_t* d_offsets, const uint32_t* d_cols,
-                 uint32_t nv, uint32_t root, uint32_t* d_level, uint32_t lanes, uint32_t block,
-                 uint64_t* d_ctl, void* stream) {
-  if (!qa || !qb || qa == qb || !d_offsets || !d_cols || !d_level || !d_ctl || nv == 0 ||
-      root >= nv || qa->kind != qb->kind || qa->w != 4 || qb->w != 4 || block == 0 ||
-      block > 256 || block % 64 || lanes == 0 || lanes % block || lanes > qa->k || lanes > qb->k)
+// Checks shared by the BFS entry points: the launch shape and co-residency
+// of the persistent kernel.
+static gq_status bfs_launch_ok(gq_kind kind, uint32_t lanes, uint32_t block) {
+  if (block == 0 || block > 256 || block % 64 || lanes == 0 || lanes % block)
     return GQ_ERR_INVALID;
-  if (qa->kind != GQ_WFQ_YMC && (qa->n < nv || qb->n < nv)) return GQ_ERR_INVALID;
   const void* fn = nullptr;
-  KIND_SWITCH(qa->kind, fn = bfs_fn<K>());
+  KIND_SWITCH(kind, fn = bfs_fn<K>());
   uint32_t resident = 0;
   gq_status st = resident_blocks_of(fn, block, &resident);
   if (st != GQ_OK) return st;
   if (lanes / block > resident) return GQ_ERR_RESIDENCY;
-  LAUNCH(bfs::k_bfs_init, dim3(grid_for(nv, kBlock, 8192)), dim3(kBlock), 0, S(stream), d_level, nv,
-         d_ctl);
+  return GQ_OK;
+}
+
+// Clear the control block, initialise the levels, run the persistent kernel.
+static gq_status bfs_launch(gq_kind kind, const gq_dev& qa, const gq_dev& qb,
+                            const uint32_t* d_offsets, const uint32_t* d_cols, uint32_t nv,
+                            uint32_t root, uint32_t* d_level, uint32_t lanes, uint32_t block,
+                            uint64_t* d_ctl, uint64_t ctl_bytes, hipStream_t s) {
+  const uint64_t words = ctl_bytes / 8;
+  const uint64_t hub_cap = words > bfs::HUB_LIST ? words - bfs::HUB_LIST : 0;
+  LAUNCH(bfs::k_bfs_ctl_clear, dim3(2), dim3(kBlock), 0, s, d_ctl);
   HIP_OK(hipGetLastError());
-  KIND_SWITCH(qa->kind, launch_bfs<K>(qa, qb, d_offsets, d_cols, nv, root, d_level, d_ctl, lanes,
-                                      block, S(stream)));
+  LAUNCH(bfs::k_bfs_init, dim3(grid_for(nv, kBlock, 8192)), dim3(kBlock), 0, s, d_level,
+         d_offsets, nv, d_ctl);
+  HIP_OK(hipGetLastError());
+  KIND_SWITCH(kind, launch_bfs<K>(qa, qb, d_offsets, d_cols, nv, root, d_level, d_ctl, hub_cap,
+                                  lanes, block, s));
   HIP_OK(hipGetLastError());
   return GQ_OK;
+}
+
+uint64_t gq_bfs_ctl_bytes(uint64_t nnz) {
+  return 8 * (bfs::HUB_LIST + nnz / bfs::HUB_MIN + 1);
+}
+
+gq_status gq_bfs(gq_queue* qa, gq_queue* qb, const uint32_t* d_offsets, const uint32_t* d_cols,
+                 uint32_t nv, uint32_t root, uint32_t* d_level, uint32_t lanes, uint32_t block,
+                 uint64_t* d_ctl, uint64_t ctl_bytes, void* stream) {
+  if (!qa || !qb || qa == qb || !d_offsets || !d_cols || !d_level || !d_ctl || nv == 0 ||
+      root >= nv || qa->kind != qb->kind || qa->w != 4 || qb->w != 4 || lanes > qa->k ||
+      lanes > qb->k || ctl_bytes < 8 * (uint64_t)bfs::CTL_MIN_WORDS || ((uintptr_t)d_ctl & 7))
+    return GQ_ERR_INVALID;
+  if (qa->kind != GQ_WFQ_YMC && (qa->n < nv || qb->n < nv)) return GQ_ERR_INVALID;
+  const gq_status st = bfs_launch_ok(qa->kind, lanes, block);
+  if (st != GQ_OK) return st;
+  return bfs_launch(qa->kind, qa->dev, qb->dev, d_offsets, d_cols, nv, root, d_level, lanes, block,
+                    d_ctl, ctl_bytes, S(stream));
 }
 
 #include "gq_serve.inc"

@@ -58,10 +58,33 @@ def assert_clean(rep: dict, hist: oracle.History = None, drain=(), prefill=(), t
     pytest.fail("oracle report: " + ", ".join(f"{k}={v}" for k, v in rep.items()))
 
 
+# Histories up to this many operations also get a linearization witness
+# (O10) unless a test asks for it at any size.
+WITNESS_MAX_OPS = 1 << 24
+
+
+def witness_report(hist: oracle.History, drain, prefill=(), capacity=0) -> dict:
+    """O10: a linearization of the whole history (with the sequential drain
+    and its final EMPTY appended), found by the witness search and confirmed
+    by the independent replay check.  lin_no_witness = 1 when none was found
+    within the search's budget (the search is complete for a found witness
+    only; O6 says whether the history is provably wrong)."""
+    rc, order, info = oracle.lin_witness(hist, prefill=prefill, drain=drain, capacity=capacity,
+                                         width=2, budget=10000)
+    bad = ""
+    if rc == 1:
+        bad = oracle.check_witness(hist, order, prefill=prefill, drain=drain, capacity=capacity)
+    if rc != 1 or bad:
+        print(f"[witness] rc={rc} info={info} check={bad!r}", flush=True)
+    return {"lin_no_witness": int(rc != 1), "lin_witness_check": int(bool(bad))}
+
+
 def check_history(hist: oracle.History, drain, prefill=(), capacity=0, token_shift=32,
-                  producer_order=True):
-    """Conservation + per-producer order + violation scan.  Returns a report
-    dict; every entry must be zero."""
+                  producer_order=True, witness=None):
+    """Conservation + per-producer order + violation scan, and a linearization
+    witness (O10) for histories of at most WITNESS_MAX_OPS operations (witness
+    True/False forces it on/off).  Returns a report dict; every entry must be
+    zero."""
     put = np.concatenate([np.asarray(prefill, dtype=np.uint64), hist.enq_ok()])
     out = np.concatenate([hist.deq_ok(), np.asarray(drain, dtype=np.uint64)])
     rep = {}
@@ -71,4 +94,8 @@ def check_history(hist: oracle.History, drain, prefill=(), capacity=0, token_shi
     rep.update({"v_" + k: v for k, v in
                 oracle.violation_scan(hist, prefill=prefill, drain=drain,
                                       capacity=capacity).items()})
+    if witness is None:
+        witness = len(hist) <= WITNESS_MAX_OPS
+    if witness:
+        rep.update(witness_report(hist, drain, prefill=prefill, capacity=capacity))
     return rep

@@ -11,7 +11,7 @@ from tests.gpu_util import torch
 pytestmark = pytest.mark.gpu
 
 
-def run_bfs(kind, off, cols, root, lanes, block=256, ymc_cells=0):
+def run_bfs(kind, off, cols, root, lanes, block=256, ymc_cells=0, ctl_bytes=None):
     import paper_2606_01693_amd as gq
     T = torch()
     nv = len(off) - 1
@@ -22,7 +22,9 @@ def run_bfs(kind, off, cols, root, lanes, block=256, ymc_cells=0):
     d_cols = T.tensor(cols.astype(np.int32), device="cuda") if len(cols) else \
         T.zeros(1, dtype=T.int32, device="cuda")
     level = T.empty(nv, dtype=T.int32, device="cuda")
-    ctl = T.zeros(512, dtype=T.int64, device="cuda")
+    if ctl_bytes is None:
+        ctl_bytes = gq.bfs_ctl_bytes(len(cols))
+    ctl = T.zeros(ctl_bytes // 8, dtype=T.int64, device="cuda")
     gq.bfs(qa, qb, d_off, d_cols, root, level, lanes, block, ctl)
     T.cuda.synchronize()
     assert qa.check_error() == gq.GQ_OK and qb.check_error() == gq.GQ_OK
@@ -34,12 +36,12 @@ def ymc_cells_for(nv, levels, lanes):
     return 4 * nv + (levels + 4) * lanes * 4 + (1 << 16)
 
 
-def check(kind, off, cols, root, lanes, block=256):
+def check(kind, off, cols, root, lanes, block=256, ctl_bytes=None):
     exp, nl, scanned = oracle.bfs(off, cols, root)
     print(f"[case] kind={kind} nv={len(off) - 1} m={len(cols)} root={root} lanes={lanes} "
-          f"levels={nl}", flush=True)
+          f"levels={nl} ctl_bytes={ctl_bytes}", flush=True)
     cells = ymc_cells_for(len(off) - 1, nl, lanes) if kind == "ymc" else 0
-    got, levels, scanned_gpu = run_bfs(kind, off, cols, root, lanes, block, cells)
+    got, levels, scanned_gpu = run_bfs(kind, off, cols, root, lanes, block, cells, ctl_bytes)
     assert np.array_equal(got, exp)
     assert levels == nl + 1 or levels == nl  # the last, empty level may be counted
     assert scanned_gpu == scanned  # every reached vertex's list is scanned once
@@ -60,13 +62,41 @@ def test_bfs_small_graphs(kind, lanes):
     check(kind, off, cols, 3, lanes)
 
 
-@pytest.mark.parametrize("kind", ["lfq", "wfq"])
+def stars(nv, centres, degree, seed):
+    """Star hubs of the given degree around `centres`, chained together, plus
+    a sparse random graph on the rest: many vertices of degree >= 1024 in one
+    level."""
+    rng = np.random.default_rng(seed)
+    src, dst = [], []
+    for i, c in enumerate(centres):
+        leaves = rng.choice(nv, size=degree, replace=False)
+        src.append(np.full(degree, c))
+        dst.append(leaves)
+        if i:
+            src.append(np.array([centres[i - 1]]))
+            dst.append(np.array([c]))
+    src.append(rng.integers(0, nv, size=4 * nv))
+    dst.append(rng.integers(0, nv, size=4 * nv))
+    return workloads._csr_from_pairs(nv, np.concatenate(src), np.concatenate(dst))
+
+
+@pytest.mark.parametrize("kind", ["lfq", "wfq", "ymc"])
+@pytest.mark.parametrize("ctl_kib", [4, 5, None])
+def test_bfs_hub_lists(kind, ctl_kib):
+    """Vertices of degree >= 1024 split over all wavefronts: with the full hub
+    list (None), with room for 128 hubs (5 KiB: the rest scanned by their own
+    wavefront) and with none (4 KiB)."""
+    off, cols = stars(1 << 15, list(range(0, 4000, 13)), 1500, 11)
+    check(kind, off, cols, 0, 4096, ctl_bytes=None if ctl_kib is None else ctl_kib * 1024)
+
+
+@pytest.mark.parametrize("kind", ["lfq", "wfq", "ymc"])
 def test_bfs_rmat22_full_size(kind):
     off, cols = workloads.rmat_graph(22, 16, seed=workloads.run_seed(4, 0))
     check(kind, off, cols, workloads.bfs_root(off, workloads.run_seed(4, 0)), 8192)
 
 
-@pytest.mark.parametrize("kind", ["lfq"])
+@pytest.mark.parametrize("kind", ["lfq", "wfq", "ymc"])
 def test_bfs_grid4096_full_size(kind):
     off, cols = workloads.grid_graph(4096, 4096)
     rng = np.random.default_rng(workloads.run_seed(4, 1))

@@ -199,7 +199,7 @@ def test_c1_role_split(kind, run):
     hist, overflow = history(h)
     assert overflow == 0
     drain = drain_fifo(q, n)
-    rep = check_history(hist, drain, capacity=n, token_shift=20)
+    rep = check_history(hist, drain, capacity=cap_of(kind, n), token_shift=20)
     assert_clean(rep, hist, drain, tag=f"c1split_{kind}_{run}")
 
 
@@ -284,7 +284,8 @@ def test_tiny_histories_linearizable(kind, chunk):
 # ---------------------------------------------------------------------------
 # Mixed 50/50 workload with recorded histories
 # ---------------------------------------------------------------------------
-def run_mix_checked(kind, n, lanes, ops, seed, slot_mode="linear", do_prefill=True, **opts):
+def run_mix_checked(kind, n, lanes, ops, seed, slot_mode="linear", do_prefill=True, witness=None,
+                    **opts):
     import paper_2606_01693_amd as gq
     T = torch()
     q = make_queue(kind, n, lanes=lanes, slot_mode=slot_mode, **opts)
@@ -310,7 +311,7 @@ def run_mix_checked(kind, n, lanes, ops, seed, slot_mode="linear", do_prefill=Tr
     expect = len(pre) + c[0] - c[1]
     drain = drain_fifo(q, n if BOUNDED[kind] else expect + 1)
     assert len(drain) == expect
-    rep = check_history(hist, drain, prefill=pre, capacity=cap_of(kind, n))
+    rep = check_history(hist, drain, prefill=pre, capacity=cap_of(kind, n), witness=witness)
     assert_clean(rep, hist, drain, pre,
                  tag=f"mix_{kind}_{n}_{lanes}_{ops}_{slot_mode}_tg{opts.get('ticket_group', 0)}")
     return c
@@ -331,11 +332,15 @@ def test_mix_history(kind, n, lanes, ops, tg):
 
 
 @pytest.mark.parametrize("kind", ["lfq", "wfq"])
-@pytest.mark.parametrize("slot_mode", ["padded", "linear"])
+@pytest.mark.parametrize("slot_mode", ["remap", "padded", "linear"])
 @pytest.mark.parametrize("n", [4, 1 << 10])
-def test_mix_history_slot_layouts(kind, slot_mode, n):
+@pytest.mark.parametrize("tg", TICKET_GROUPS)
+def test_mix_history_slot_layouts(kind, slot_mode, n, tg):
+    """Every slot layout of the ring queues (remapped lines, padded, linear)
+    under both ticket modes passes O3/O4/O6 on the whole history."""
     lanes = 1024 if n < 64 else 16384
-    run_mix_checked(kind, n, lanes, 32, workloads.run_seed(2, 77), slot_mode=slot_mode)
+    run_mix_checked(kind, n, lanes, 32, workloads.run_seed(2, 77), slot_mode=slot_mode,
+                    ticket_group=tg)
 
 
 @pytest.mark.parametrize("kind", KINDS)
@@ -399,8 +404,11 @@ def test_mix_timed_kernel_conserves(kind, tg):
 @pytest.mark.parametrize("tg", TICKET_GROUPS)
 def test_mix_full_size(kind, tg):
     """The benchmark's configuration: capacity 2^20, 2048 x 256 lanes, 2^26
-    operations, prefill n/2; the full history is checked."""
-    run_mix_checked(kind, 1 << 20, 2048 * 256, 128, workloads.run_seed(2, 0), ticket_group=tg)
+    operations, prefill n/2; the full history is checked, and in the
+    benchmark's own launch (default ticket group) a linearization of all
+    2^26 operations plus the drain is found and confirmed (O10)."""
+    run_mix_checked(kind, 1 << 20, 2048 * 256, 128, workloads.run_seed(2, 0), ticket_group=tg,
+                    witness=(tg == 0))
 
 
 # ---------------------------------------------------------------------------
