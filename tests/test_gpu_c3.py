@@ -69,11 +69,6 @@ def c3_run(kind, n, waves, prod_waves, log2_inv_p, items, seed, hist_per_lane=0,
 @pytest.mark.parametrize("prod_waves", [128, 512, 896])
 @pytest.mark.parametrize("log2_inv_p", [0, 1, 6])
 def test_c3_full_size_conservation(kind, prod_waves, log2_inv_p):
-    if kind == "ymc" and prod_waves == 128:
-        pytest.skip("G-WFQ-YMC 128:896: polling through ticket fetch-and-adds exhausted even "
-                    "2^30 pool cells, and with an empty pre-check a slow dequeue's helping walk "
-                    "(one cell at a time behind H) once hung for 150 s; kept off the GPU until "
-                    "the bounded walk and the ticket grab below T are run once")
     T = torch()
     seed = workloads.run_seed(3, prod_waves + log2_inv_p)
     q, role, quota, target, c, _ = c3_run(kind, 1 << 16, 1024, prod_waves, log2_inv_p,
@@ -97,10 +92,6 @@ def test_c3_full_size_conservation(kind, prod_waves, log2_inv_p):
 @pytest.mark.parametrize("log2_inv_p", [0, 6])
 def test_c3_shape_histories(kind, prod_waves, log2_inv_p):
     """64 wavefronts, capacity 2^10, 2^15 items, whole history recorded."""
-    if kind == "ymc" and prod_waves == 8:
-        pytest.skip("G-WFQ-YMC 8:56: polling through ticket fetch-and-adds exhausted its pool, "
-                    "and the 1:7 shape's helping walk once hung (see the full-size case); kept "
-                    "off the GPU until the bounded walk and the ticket grab below T are run once")
     seed = workloads.run_seed(3, 100 + prod_waves + log2_inv_p)
     n = 1 << 10
     q, role, quota, target, c, h = c3_run(kind, n, 64, prod_waves, log2_inv_p, 1 << 15, seed,
