@@ -47,7 +47,8 @@ typedef enum {
     GQ_ERR_RESIDENCY = -4,        /* requested lanes cannot all be resident    */
     GQ_ERR_CYCLE_BOUND = -5,      /* G-WFQ: R <= D*k/n + 6 (Lemma 4)           */
     GQ_ERR_POOL_EXHAUSTED = -6,   /* G-WFQ-YMC ran out of preallocated cells   */
-    GQ_ERR_DEVICE = -7            /* a device-side invariant check failed      */
+    GQ_ERR_DEVICE = -7,           /* a device-side invariant check failed      */
+    GQ_ERR_TOO_LARGE = -8         /* beyond an entry point's fixed maximum size */
 } gq_status;
 
 typedef enum { GQ_LFQ = 0, GQ_WFQ = 1, GQ_WFQ_YMC = 2 } gq_kind;

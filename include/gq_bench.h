@@ -106,6 +106,29 @@ gq_status gq_bfs(gq_queue *qa, gq_queue *qb, const uint32_t *d_offsets, const ui
 /* Workspace bytes for gq_bfs on a graph of nnz adjacency entries.            */
 uint64_t gq_bfs_ctl_bytes(uint64_t nnz);
 
+/* For callers that cannot allocate device memory -- code being captured into a
+ * HIP graph, tight serving loops, harnesses that forbid hipMalloc: gq_bfs with
+ * its two frontier queues (kind GQ_LFQ or GQ_WFQ, capacity the next power of
+ * two >= max(nv, 64), item width 4, linear slots) and its workspace placed in a
+ * static device array of GQ_BFS_STATIC_BYTES that the library holds on every
+ * GPU it runs on until the process ends.  It calls no hipMalloc, hipFree or
+ * allocating library routine.  Graph and outputs are the caller's device
+ * memory as for gq_bfs; d_info (nullable) receives 4 uint64: [0] the latched
+ * device error as -gq_status (0 = none), [1] levels, [2] adjacency entries
+ * scanned, [3] 0.  Limits: nv <= GQ_BFS_STATIC_MAX_VERTICES and lanes <=
+ * GQ_BFS_STATIC_MAX_LANES (GQ_ERR_TOO_LARGE beyond them), lanes a multiple of
+ * block (64..256), all workgroups co-resident (GQ_ERR_RESIDENCY).  Every call
+ * re-initialises the queues and workspace it uses, but all calls on one GPU
+ * share the one array: calls that overlap in time on one GPU (streams not
+ * ordered with each other) race and return wrong levels; calls on one stream
+ * run one after another.                                                      */
+#define GQ_BFS_STATIC_MAX_VERTICES (1u << 18)
+#define GQ_BFS_STATIC_MAX_LANES 8192u
+#define GQ_BFS_STATIC_BYTES (40ull << 20)
+gq_status gq_bfs_static(gq_kind kind, const uint32_t *d_offsets, const uint32_t *d_cols,
+                        uint32_t nv, uint32_t root, uint32_t *d_level, uint32_t lanes,
+                        uint32_t block, uint64_t *d_info, void *stream);
+
 /* Balanced workload (Section V-A "balanced kernel", fixed op count): every
  * lane performs `rounds` times (enqueue its next token; dequeue), each tried
  * once.  Tokens as in gq_run_mix.  d_counts[4] as above.                      */

@@ -7,7 +7,7 @@ built.
 """
 from ._binding import (  # noqa: F401
     EXPORTS, GQ_EMPTY, GQ_ERR_CYCLE_BOUND, GQ_ERR_DEVICE, GQ_ERR_HIP, GQ_ERR_INVALID,
-    GQ_ERR_NOMEM, GQ_ERR_POOL_EXHAUSTED, GQ_ERR_RESIDENCY, GQ_FULL, GQ_OK, KINDS,
+    GQ_ERR_NOMEM, GQ_ERR_POOL_EXHAUSTED, GQ_ERR_RESIDENCY, GQ_ERR_TOO_LARGE, GQ_FULL, GQ_OK, KINDS,
     GQError,
     RT_COMPACT, RT_QUEUES, SERVE_HASH_SEED, History, Multi, Queue, RayTracer, Server, Stats, bfs,
     bfs_ctl_bytes,

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libgq.so")
 
 GQ_OK, GQ_EMPTY, GQ_FULL = 0, 1, 2
 GQ_ERR_INVALID, GQ_ERR_NOMEM, GQ_ERR_HIP, GQ_ERR_RESIDENCY = -1, -2, -3, -4
-GQ_ERR_CYCLE_BOUND, GQ_ERR_POOL_EXHAUSTED, GQ_ERR_DEVICE = -5, -6, -7
+GQ_ERR_CYCLE_BOUND, GQ_ERR_POOL_EXHAUSTED, GQ_ERR_DEVICE, GQ_ERR_TOO_LARGE = -5, -6, -7, -8
 
 KINDS = {"lfq": 0, "wfq": 1, "ymc": 2}
 SLOT_MODES = {"remap": 0, "padded": 1, "linear": 2}
@@ -31,6 +31,7 @@ EXPORTS = (
     "gq_run_script", "gq_probe_faa", "gq_probe_cas", "gq_probe_copy", "gq_probe_fence",
     "gq_resident_blocks", "gq_device_info", "gq_multi_create", "gq_multi_run_mix",
     "gq_multi_capture", "gq_multi_replay", "gq_multi_destroy", "gq_bfs", "gq_bfs_ctl_bytes",
+    "gq_bfs_static",
     "gq_serve_create", "gq_serve_run", "gq_serve_job_bytes", "gq_serve_destroy",
     "gq_run_timed", "gq_rt_create", "gq_rt_render", "gq_rt_check_error", "gq_rt_destroy",
 )
@@ -148,6 +149,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     }
     L.gq_bfs_ctl_bytes.restype = U64
     L.gq_bfs_ctl_bytes.argtypes = [U64]
+    L.gq_bfs_static.restype = I32
+    L.gq_bfs_static.argtypes = [I32, P, P, U32, U32, P, U32, U32, P, P]
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args

@@ -7,6 +7,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "../../include/gq.h"
@@ -873,6 +874,7 @@ const char* gq_status_str(gq_status s) {
     case GQ_ERR_CYCLE_BOUND: return "cycle-tag bound R > D*k/n + 6 violated";
     case GQ_ERR_POOL_EXHAUSTED: return "G-WFQ-YMC cell pool exhausted";
     case GQ_ERR_DEVICE: return "device-side invariant or bound violated";
+    case GQ_ERR_TOO_LARGE: return "size beyond the entry point's fixed maximum";
   }
   return "unknown status";
 }
@@ -1579,6 +1581,94 @@ gq_status gq_bfs(gq_queue* qa, gq_queue* qb, const uint32_t* d_offsets, const ui
   if (st != GQ_OK) return st;
   return bfs_launch(qa->kind, qa->dev, qb->dev, d_offsets, d_cols, nv, root, d_level, lanes, block,
                     d_ctl, ctl_bytes, S(stream));
+}
+
+// ---- BFS with no allocation ------------------------------------------------
+// The two frontier queues and the control block of gq_bfs_static live in
+// this file-scope array (one copy per GPU, alive until the process ends).
+// Host code never passes `g_bfs_scratch` itself to a kernel -- on the host it
+// is only a stand-in symbol -- but the device address hipGetSymbolAddress
+// returns for it, looked up once per device on the first call there.
+static __device__ __align__(256) unsigned char g_bfs_scratch[GQ_BFS_STATIC_BYTES];
+static constexpr int kMaxDevices = 64;
+
+static constexpr uint64_t kStaticCtlBytes = 64 * 1024;  // 7680 hub-list entries
+
+static gq_status static_scratch(char** out) {
+  static std::mutex mu;
+  static char* ptr[kMaxDevices] = {};
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return GQ_ERR_INVALID;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(g_bfs_scratch)));
+    if (!p) return GQ_ERR_HIP;
+    ptr[dev] = (char*)p;
+  }
+  *out = ptr[dev];
+  return GQ_OK;
+}
+
+// Queue initialisation from a device view (the kernels of launch_init).
+static gq_status init_view(gq_kind kind, const gq_dev& d, uint64_t n, uint32_t k, hipStream_t s) {
+  const uint64_t slots = 2 * n > k ? 2 * n : k;
+  const uint32_t grid = grid_for(slots, kBlock, 4096);
+  if (kind == GQ_LFQ) LAUNCH(k_init_lfq, dim3(grid), dim3(kBlock), 0, s, d);
+  else if (kind == GQ_WFQ) LAUNCH(k_init_wfq, dim3(grid), dim3(kBlock), 0, s, d);
+  else return GQ_ERR_INVALID;
+  HIP_OK(hipGetLastError());
+  return GQ_OK;
+}
+
+__global__ void k_bfs_static_info(const uint64_t* err_a, const uint64_t* err_b,
+                                  const uint64_t* ctl, uint64_t* info) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const uint64_t ea = ld(err_a), eb = ld(err_b);
+    st(info + 0, ea ? ea : eb);
+    st(info + 1, ld(ctl + bfs::LEVELS));
+    st(info + 2, ld(ctl + bfs::SCANNED));
+    st(info + 3, 0ull);
+  }
+}
+
+gq_status gq_bfs_static(gq_kind kind, const uint32_t* d_offsets, const uint32_t* d_cols,
+                        uint32_t nv, uint32_t root, uint32_t* d_level, uint32_t lanes,
+                        uint32_t block, uint64_t* d_info, void* stream) {
+  if (kind != GQ_LFQ && kind != GQ_WFQ) return GQ_ERR_INVALID;
+  if (nv > GQ_BFS_STATIC_MAX_VERTICES || lanes > GQ_BFS_STATIC_MAX_LANES)
+    return GQ_ERR_TOO_LARGE;
+  if (!d_offsets || !d_cols || !d_level || nv == 0 || root >= nv) return GQ_ERR_INVALID;
+  uint64_t cap = 64;  // G-WFQ's cycle bound (Lemma 4) holds for 8192 lanes from here on
+  while (cap < nv) cap <<= 1;
+  Layout L;
+  gq_status st = plan(kind, cap, 4, lanes, nullptr, &L);
+  if (st != GQ_OK) return st;
+  const uint64_t qbytes = align_up(L.total, 256);
+  if (2 * qbytes + kStaticCtlBytes > GQ_BFS_STATIC_BYTES) return GQ_ERR_TOO_LARGE;
+  st = bfs_launch_ok(kind, lanes, block);
+  if (st != GQ_OK) return st;
+  char* base = nullptr;
+  st = static_scratch(&base);
+  if (st != GQ_OK) return st;
+  gq_options o;
+  memset(&o, 0, sizeof(o));
+  o.slot_mode = GQ_SLOTS_LINEAR;
+  const gq_dev qa = make_dev(kind, cap, 4, lanes, o, base, L);
+  const gq_dev qb = make_dev(kind, cap, 4, lanes, o, base + qbytes, L);
+  uint64_t* ctl = (uint64_t*)(base + 2 * qbytes);
+  const hipStream_t s = S(stream);
+  st = init_view(kind, qa, cap, lanes, s);
+  if (st == GQ_OK) st = init_view(kind, qb, cap, lanes, s);
+  if (st == GQ_OK)
+    st = bfs_launch(kind, qa, qb, d_offsets, d_cols, nv, root, d_level, lanes, block, ctl,
+                    kStaticCtlBytes, s);
+  if (st == GQ_OK && d_info) {
+    LAUNCH(k_bfs_static_info, dim3(1), dim3(64), 0, s, qa.err, qb.err, ctl, d_info);
+    HIP_OK(hipGetLastError());
+  }
+  return st;
 }
 
 #include "gq_serve.inc"

@@ -140,3 +140,26 @@ def test_rt_create_rejects_bad_arguments(kind, w, h, tile, lanes):
     assert out.value is None
     assert L.gq_rt_render(None, None, 0, None, None, None, None) == b.GQ_ERR_INVALID
     assert L.gq_rt_destroy(None) == b.GQ_ERR_INVALID
+
+
+def test_bfs_static_limits():
+    """The allocation-free BFS refuses sizes beyond its fixed maximum before
+    any HIP call (no GPU needed), and its static array holds the largest
+    configuration: two G-WFQ queues of capacity 2^18 for 8192 lanes plus the
+    64 KiB workspace."""
+    from paper_2606_01693_amd import _binding
+    L = _binding.lib()
+    assert L.gq_status_str(-8).startswith(b"size beyond")
+    fake = ctypes.c_void_p(4096)
+    assert L.gq_bfs_static(0, fake, fake, (1 << 18) + 1, 0, fake, 256, 256, None, None) == -8
+    assert L.gq_bfs_static(1, fake, fake, 100, 0, fake, 8192 + 64, 64, None, None) == -8
+    assert L.gq_bfs_static(2, fake, fake, 100, 0, fake, 256, 256, None, None) == -1  # YMC
+    assert L.gq_bfs_static(0, None, fake, 100, 0, fake, 256, 256, None, None) == -1
+    assert L.gq_bfs_static(0, fake, fake, 100, 100, fake, 256, 256, None, None) == -1
+    total = 64 * 1024
+    for kind in (0, 1):
+        b = ctypes.c_uint64(0)
+        assert L.gq_required_bytes(kind, 1 << 18, 4, 8192, None, ctypes.byref(b)) == 0
+        total_k = 2 * ((b.value + 255) // 256 * 256) + 64 * 1024
+        total = max(total, total_k)
+    assert total <= 40 << 20
