@@ -609,7 +609,7 @@ def bench_timed(gq, torch, kinds, reps=5, warmup_us=1000, window_us=5000):
         q = gq.Queue(kind, CAP, item_width=ITEM_BYTES, max_threads=1 << 15,
                      ymc_pool_cells=(1 << 28) if kind == "ymc" else 0)
         pre = torch.arange(1, CAP // 2 + 1, dtype=torch.int64, device="cuda") | (0xFFFFFFFF << 32)
-        counts = torch.zeros(4, dtype=torch.int64, device="cuda")
+        counts = torch.zeros(10, dtype=torch.int64, device="cuda")
         ctl = torch.zeros(4, dtype=torch.int64, device="cuda")
         modes = [("balanced", 50), ("split", 25), ("split", 50), ("split", 75)]
         if kind == "wfq":
@@ -647,8 +647,7 @@ def bench_c3(gq, torch, kinds=("lfq", "wfq", "ymc"), items=1 << 23, cap=1 << 16,
     probability 1, 1/2 or 1/64; producers retry on FULL, consumers on EMPTY,
     until 2^23 items went through.  Mops/s counts successful operations
     (2 x items) over the kernel time; conservation is checked through the
-    driver's multiset checksums.  Left out: G-WFQ-YMC with 57,344 polling
-    consumers, which exhaust its pool (the same limit as the C3 tests)."""
+    driver's multiset checksums."""
     import workloads
     lanes = waves * 64
     out = {}
@@ -657,8 +656,6 @@ def bench_c3(gq, torch, kinds=("lfq", "wfq", "ymc"), items=1 << 23, cap=1 << 16,
                      ymc_pool_cells=(1 << 31) if kind == "ymc" else 0)
         for prod in (128, 512, 896):
             for l2p in (0, 1, 6):
-                if kind == "ymc" and prod == 128:
-                    continue
                 seed = workloads.run_seed(3, prod + l2p)
                 mask = workloads.producer_waves(seed, waves, prod)
                 role = torch.tensor(np.repeat(np.where(mask, 0, 1), 64).astype(np.uint8),

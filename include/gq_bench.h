@@ -77,14 +77,17 @@ gq_status gq_run_mix(gq_queue *q, uint64_t seed, uint32_t lanes, uint32_t ops_pe
  * kernel launch; d_counts[8 * i + 0..7] += queue i's eight gq_run_mix
  * counts {ok_enq, ok_deq, full, empty, S1_deq, S2_deq, S1_enq, S2_enq}.  gq_multi_capture records (seed bump + that launch) into a
  * hipGraph on `stream` (which must not be the legacy default stream);
- * gq_multi_replay launches it (each replay advances the seed by one).       */
+ * gq_multi_replay launches it (each replay advances the seed by one).  With a
+ * history (nullable) the captured launch records every operation into it, so
+ * each replay overwrites the history with its own (lanes of all queues in
+ * launch order).                                                             */
 typedef struct gq_multi gq_multi;
 gq_status gq_multi_create(uint32_t nq, gq_queue *const *queues, const uint32_t *lanes_per_queue,
                           uint32_t block, gq_multi **out);
 gq_status gq_multi_run_mix(gq_multi *m, uint64_t seed, uint32_t ops_per_lane, uint64_t *d_counts,
                            const gq_history *hist, void *stream);
 gq_status gq_multi_capture(gq_multi *m, uint64_t seed, uint32_t ops_per_lane, uint64_t *d_counts,
-                           void *stream);
+                           const gq_history *hist, void *stream);
 gq_status gq_multi_replay(gq_multi *m, void *stream);
 gq_status gq_multi_destroy(gq_multi *m);
 
@@ -166,13 +169,19 @@ gq_status gq_run_prodcons(gq_queue *q, uint64_t seed, uint32_t lanes, uint32_t b
  * operation counts when it completes inside the window.  mode 0 (balanced):
  * every lane alternates enqueue and dequeue; mode 1 (split): the first
  * prod_pct percent of the wavefronts only enqueue, the rest only dequeue.
- * Each operation is tried once; tokens as in gq_run_mix.  d_counts[4] +=
- * {enqueues OK in the window, dequeues OK in the window, FULL, EMPTY} (the
- * last two over the whole run).  d_ctl: caller-owned device memory of at
- * least 8 bytes (the shared start time), cleared by the call.               */
+ * Each operation is tried once; tokens as in gq_run_mix.  d_counts[10] +=
+ * {enqueues OK in the window, dequeues OK in the window, FULL, EMPTY,
+ * S1_deq, S2_deq, S1_enq, S2_enq, enqueues OK, dequeues OK} (all but the
+ * first two over the whole run; S1/S2 the wrapping sums of v and v*v of the
+ * items dequeued, and of the tokens enqueued, as in gq_run_mix).
+ * d_lane_enq (nullable): uint32 per lane, its successful enqueues.  hist
+ * (nullable): every operation recorded; a lane stops when its history row
+ * (per_lane entries) is full.  d_ctl: caller-owned device memory of at least
+ * 8 bytes (the shared start time), cleared by the call.                      */
 gq_status gq_run_timed(gq_queue *q, uint32_t mode, uint32_t lanes, uint32_t prod_pct,
                        uint32_t warmup_us, uint32_t window_us, uint64_t *d_counts,
-                       uint64_t *d_ctl, void *stream);
+                       uint64_t *d_ctl, uint32_t *d_lane_enq, const gq_history *hist,
+                       void *stream);
 
 /* Scripted run for small linearizability tests: lane g (< lanes <= 1024)
  * executes n_ops[g] operations from ops[g * max_ops ...] (0 enqueue,

@@ -3,7 +3,8 @@
 Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
 may import this package.  It shares no code with the HIP queues: it loads its
 own C library (gq_oracle.c, built with gcc by ``build()``) and a pure-Python
-exhaustive linearizability search (linearize.py).
+exhaustive linearizability search (linearize.py) and a linearization witness
+search for large histories (gq_linsearch.c, in the same library).
 
 What it checks is the paper's correctness statement: histories are
 linearizable with respect to the sequential FIFO model (Section IV), and every

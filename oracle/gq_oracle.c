@@ -31,7 +31,8 @@
  *   O6     orc_violation_scan   sound violation patterns on large histories
  *   O7     orc_bfs              sequential queue BFS (Section V-B)
  *          orc_locked_queue_run host mutex + ring baseline (measurement only)
- * The brute-force linearizability search (O5) is in linearize.py.
+ * The brute-force linearizability search (O5) is in linearize.py; the
+ * linearization witness search for large histories (O10) in gq_linsearch.c.
  */
 #include <pthread.h>
 #include <stdint.h>

@@ -133,12 +133,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gq_device_info": [P, P, P, U32],
         "gq_multi_create": [U32, P, P, U32, P],
         "gq_multi_run_mix": [P, U64, U32, P, P, P],
-        "gq_multi_capture": [P, U64, U32, P, P],
+        "gq_multi_capture": [P, U64, U32, P, P, P],
         "gq_multi_replay": [P, P],
         "gq_multi_destroy": [P],
         "gq_bfs": [P, P, P, P, U32, U32, P, U32, U32, P, U64, P],
         "gq_serve_create": [U32, U32, I32, U64, U32, U32, P],
-        "gq_run_timed": [P, U32, U32, U32, U32, U32, P, P, P],
+        "gq_run_timed": [P, U32, U32, U32, U32, U32, P, P, P, P, P],
         "gq_serve_run": [P, U32, P, P, U32, P],
         "gq_serve_job_bytes": [P, U32, U64, P],
         "gq_serve_destroy": [P],
@@ -373,13 +373,21 @@ class Queue:
                                      _stream(stream)), "gq_run_prodcons")
 
     def run_timed(self, mode: str, lanes: int, counts, ctl, prod_pct: int = 50,
-                  warmup_us: int = 1000, window_us: int = 5000, stream=None):
-        """Fixed-duration run; mode 'balanced' or 'split'.  counts: 4 int64
-        words (added to); ctl: at least one int64 word of scratch."""
-        _need_words(counts, 4, "run_timed")
+                  warmup_us: int = 1000, window_us: int = 5000, lane_enq=None,
+                  hist: History = None, stream=None):
+        """Fixed-duration run; mode 'balanced' or 'split'.  counts: 10 int64
+        words (added to; see gq_run_timed); ctl: at least one int64 word of
+        scratch; lane_enq: optional int32 per lane; hist: optional History."""
+        _need_words(counts, 10, "run_timed")
         _need_words(ctl, 1, "run_timed ctl")
+        if lane_enq is not None and lane_enq.numel() * lane_enq.element_size() < 4 * lanes:
+            raise ValueError("run_timed: lane_enq needs one int32 per lane")
+        _need_hist(hist, lanes, "run_timed")
+        hc = hist.c() if hist is not None else None
         _check(lib().gq_run_timed(self._h, {"balanced": 0, "split": 1}[mode], lanes, prod_pct,
                                   warmup_us, window_us, _ptr(counts), _ptr(ctl),
+                                  _ptr(lane_enq) if lane_enq is not None else None,
+                                  ctypes.byref(hc) if hc is not None else None,
                                   _stream(stream)), "gq_run_timed")
 
     def run_script(self, lanes: int, spread: bool, ops, args, pauses, n_ops, max_ops: int,
@@ -447,10 +455,14 @@ class Multi:
                                       ctypes.byref(hc) if hc is not None else None,
                                       _stream(stream)), "gq_multi_run_mix")
 
-    def capture(self, seed: int, ops_per_lane: int, counts, stream):
+    def capture(self, seed: int, ops_per_lane: int, counts, stream, hist: History = None):
         _need_words(counts, 8 * len(self.queues), "Multi.capture")
-        _check(lib().gq_multi_capture(self._h, seed, ops_per_lane, _ptr(counts), _stream(stream)),
-               "gq_multi_capture")
+        _need_hist(hist, sum(self.lanes), "Multi.capture")
+        hc = hist.c() if hist is not None else None
+        self._hist_c = hc  # the graph keeps the history's device pointers
+        _check(lib().gq_multi_capture(self._h, seed, ops_per_lane, _ptr(counts),
+                                      ctypes.byref(hc) if hc is not None else None,
+                                      _stream(stream)), "gq_multi_capture")
 
     def replay(self, stream):
         _check(lib().gq_multi_replay(self._h, _stream(stream)), "gq_multi_replay")

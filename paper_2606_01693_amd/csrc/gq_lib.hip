@@ -641,11 +641,17 @@ __global__ void k_prodcons(gq_dev q, uint64_t seed, const uint8_t* role, uint32_
 // ---- fixed-duration runs -----------------------------------------------------
 // Every lane reads the shared start time (the first lane to arrive sets it),
 // then works until start + warmup + window.  The clock is the scalar 100 MHz
-// counter, so all lanes of a wavefront leave the loop together.
-template <int KIND>
+// counter, so all lanes of a wavefront leave the loop together.  Besides the
+// window counts the kernel keeps the whole run's books for the oracle: OK
+// counts, the dequeued items' wrapping sums of v and v * v, the enqueued
+// tokens' sums in closed form (token_sums), per-lane enqueue counts, and --
+// with a history -- every operation; a lane whose history is full stops (all
+// lanes of a wavefront reach that point together).
+template <int KIND, bool REC>
 __global__ __launch_bounds__(256) void k_timed(gq_dev q, uint32_t mode, uint32_t prod_waves,
                                                uint64_t warm_ticks, uint64_t win_ticks,
-                                               uint64_t* counts, uint64_t* ctl) {
+                                               uint64_t* counts, uint64_t* ctl,
+                                               uint32_t* lane_enq, Rec rec) {
   const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   uint64_t start = ld(ctl);
   if (start == 0) {
@@ -655,18 +661,31 @@ __global__ __launch_bounds__(256) void k_timed(gq_dev q, uint32_t mode, uint32_t
   }
   const uint64_t w0 = start + warm_ticks, w1 = w0 + win_ticks;
   const bool producer = (g >> 6) < prod_waves;
-  uint32_t seq = 0, ok_e = 0, ok_d = 0, full = 0, empty = 0, cf = 0;
-  for (uint32_t r = 0;; r++) {
+  uint32_t seq = 0, ok_e = 0, ok_d = 0, all_d = 0, full = 0, empty = 0, cf = 0;
+  uint64_t s1d = 0, s2d = 0;
+  uint32_t r = 0;
+  for (;; r++) {
+    if (REC && r >= rec.h.per_lane) break;
     const bool enq = mode == 0 ? (r & 1) == 0 : producer;
+    const uint64_t t0 = REC ? stamp() : 0;
     int st;
+    uint64_t v = 0;
     if (enq) {
-      st = gq_enqueue_k<KIND>(q, (g << 32) | (uint64_t)(seq + 1), (uint32_t)g, cf);
+      v = (g << 32) | (uint64_t)(seq + 1);
+      st = gq_enqueue_k<KIND>(q, v, (uint32_t)g, cf);
       if (st == GQ_OK) seq++;
     } else {
-      uint64_t v = 0;
       st = gq_dequeue_k<KIND>(q, &v, (uint32_t)g, cf);
+      if (st == GQ_OK) {
+        all_d++;
+        s1d += v;
+        s2d += v * v;
+      } else {
+        v = 0;
+      }
     }
-    const uint64_t t = stamp();
+    const uint64_t t = REC ? end_stamp(q) : stamp();
+    if (REC) rec.put(g, r, enq ? 0 : 1, st, v, t0, t);
     if (st == GQ_OK) {
       if (t >= w0 && t < w1) {
         if (enq) ok_e++; else ok_d++;
@@ -674,12 +693,25 @@ __global__ __launch_bounds__(256) void k_timed(gq_dev q, uint32_t mode, uint32_t
     } else {
       if (enq) full++; else empty++;
     }
-    if (t >= w1) break;
+    if (t >= w1) {
+      r++;
+      break;
+    }
   }
+  if (REC && rec.h.count) rec.h.count[g] = r;
+  if (lane_enq) lane_enq[g] = seq;
+  uint64_t s1e, s2e;
+  token_sums(g, seq, s1e, s2e);
   wave_add(counts + 0, ok_e);
   wave_add(counts + 1, ok_d);
   wave_add(counts + 2, full);
   wave_add(counts + 3, empty);
+  wave_add(counts + 4, s1d);
+  wave_add(counts + 5, s2d);
+  wave_add(counts + 6, s1e);
+  wave_add(counts + 7, s2e);
+  wave_add(counts + 8, seq);
+  wave_add(counts + 9, all_d);
   wave_add(q.stats + S_CAS_FAIL, cf);
 }
 
@@ -1246,14 +1278,36 @@ gq_status gq_run_prodcons(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t b
   return GQ_OK;
 }
 
+template <int KIND>
+static const void* timed_fn(bool hist) {
+  return hist ? (const void*)k_timed<KIND, true> : (const void*)k_timed<KIND, false>;
+}
+
+template <int KIND>
+static void launch_timed(gq_queue* q, uint32_t lanes, uint32_t mode, uint32_t prod_waves,
+                         uint64_t warm, uint64_t win, uint64_t* counts, uint64_t* ctl,
+                         uint32_t* lane_enq, const gq_history* hist, hipStream_t s) {
+  const Rec rec = make_rec(hist);
+  const dim3 grid(lanes / kBlock), block(kBlock);
+  if (hist)
+    LAUNCH((k_timed<KIND, true>), grid, block, 0, s, q->dev, mode, prod_waves, warm, win, counts,
+           ctl, lane_enq, rec);
+  else
+    LAUNCH((k_timed<KIND, false>), grid, block, 0, s, q->dev, mode, prod_waves, warm, win, counts,
+           ctl, lane_enq, rec);
+}
+
 gq_status gq_run_timed(gq_queue* q, uint32_t mode, uint32_t lanes, uint32_t prod_pct,
                        uint32_t warmup_us, uint32_t window_us, uint64_t* d_counts,
-                       uint64_t* d_ctl, void* stream) {
+                       uint64_t* d_ctl, uint32_t* d_lane_enq, const gq_history* hist,
+                       void* stream) {
   if (!q || !d_counts || !d_ctl || mode > 1 || lanes == 0 || lanes % kBlock || lanes > q->k ||
       prod_pct > 100 || window_us == 0)
     return GQ_ERR_INVALID;
+  if (hist && (!hist->val || !hist->call || !hist->ret || !hist->opst || hist->per_lane == 0))
+    return GQ_ERR_INVALID;
   const void* fn = nullptr;
-  KIND_SWITCH(q->kind, fn = (const void*)k_timed<K>);
+  KIND_SWITCH(q->kind, fn = timed_fn<K>(hist != nullptr));
   uint32_t resident = 0;
   gq_status st = resident_blocks_of(fn, kBlock, &resident);
   if (st != GQ_OK) return st;
@@ -1262,8 +1316,8 @@ gq_status gq_run_timed(gq_queue* q, uint32_t mode, uint32_t lanes, uint32_t prod
   const uint32_t prod_waves = mode == 0 ? waves : (uint32_t)((uint64_t)waves * prod_pct / 100);
   HIP_OK(hipMemsetAsync(d_ctl, 0, sizeof(uint64_t), S(stream)));
   const uint64_t warm = (uint64_t)warmup_us * 100, win = (uint64_t)window_us * 100;
-  KIND_SWITCH(q->kind, LAUNCH(k_timed<K>, dim3(lanes / kBlock), dim3(kBlock), 0, S(stream),
-                              q->dev, mode, prod_waves, warm, win, d_counts, d_ctl));
+  KIND_SWITCH(q->kind, launch_timed<K>(q, lanes, mode, prod_waves, warm, win, d_counts, d_ctl,
+                                       d_lane_enq, hist, S(stream)));
   HIP_OK(hipGetLastError());
   return GQ_OK;
 }
@@ -1466,8 +1520,9 @@ gq_status gq_multi_run_mix(gq_multi* m, uint64_t seed, uint32_t ops_per_lane, ui
 }
 
 gq_status gq_multi_capture(gq_multi* m, uint64_t seed, uint32_t ops_per_lane, uint64_t* d_counts,
-                           void* stream) {
+                           const gq_history* hist, void* stream) {
   if (!m || !d_counts || !stream) return GQ_ERR_INVALID;
+  if (hist && (!hist->val || !hist->call || !hist->ret || !hist->opst)) return GQ_ERR_INVALID;
   if (m->captured) {
     (void)hipGraphExecDestroy(m->exec);
     (void)hipGraphDestroy(m->graph);
@@ -1480,9 +1535,9 @@ gq_status gq_multi_capture(gq_multi* m, uint64_t seed, uint32_t ops_per_lane, ui
   LAUNCH(k_seed, dim3(1), dim3(64), 0, S(stream), m->d_seed, 0ull, 1u);
   gq_status st = GQ_OK;
   switch (m->kind) {
-    case GQ_LFQ: launch_multi<GQ_LFQ>(m, ops_per_lane, d_counts, nullptr, S(stream)); break;
-    case GQ_WFQ: launch_multi<GQ_WFQ>(m, ops_per_lane, d_counts, nullptr, S(stream)); break;
-    case GQ_WFQ_YMC: launch_multi<GQ_WFQ_YMC>(m, ops_per_lane, d_counts, nullptr, S(stream)); break;
+    case GQ_LFQ: launch_multi<GQ_LFQ>(m, ops_per_lane, d_counts, hist, S(stream)); break;
+    case GQ_WFQ: launch_multi<GQ_WFQ>(m, ops_per_lane, d_counts, hist, S(stream)); break;
+    case GQ_WFQ_YMC: launch_multi<GQ_WFQ_YMC>(m, ops_per_lane, d_counts, hist, S(stream)); break;
     default: st = GQ_ERR_INVALID;
   }
   hipGraph_t g = nullptr;

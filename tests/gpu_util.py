@@ -37,6 +37,26 @@ def drain_fifo(q, max_items: int):
     return val[:first_empty].copy()
 
 
+def prefill(q, items):
+    """Enqueue `items` in list order (one lane, sequentially), so the oracle
+    may take them as the queue's initial contents in that order; a batch
+    enqueue leaves the order within the batch unspecified."""
+    T = torch()
+    if len(items) == 0:
+        return
+    t = T.tensor(np.asarray(items, dtype=np.uint64).view(np.int64), device="cuda")
+    # one lane enqueues them in list order
+    ops = T.zeros(len(items), dtype=T.uint8, device="cuda")
+    pauses = T.zeros(len(items), dtype=T.int16, device="cuda")
+    n_ops = T.tensor([len(items)], dtype=T.int32, device="cuda")
+    import paper_2606_01693_amd as gq
+    h = gq.History(1, len(items))
+    q.run_script(1, False, ops, t, pauses, n_ops, len(items), h)
+    T.cuda.synchronize()
+    _, _, s, _, _, _, _ = h.to_numpy()
+    assert (s == gq.GQ_OK).all()
+
+
 def history(h) -> tuple:
     proc, op, st, val, call, ret, overflow = h.to_numpy()
     return oracle.History(proc, op, st, val, call, ret), overflow

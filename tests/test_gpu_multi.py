@@ -99,3 +99,56 @@ def test_multi_queue_graph_replays(kind):
         prod = (np.asarray(got, dtype=np.uint64) >> np.uint64(32)).astype(np.int64)
         assert ((prod >= lane0) & (prod < lane0 + lanes[i])).all()
     m.close()
+
+
+@pytest.mark.parametrize("kind", ["lfq", "wfq", "ymc"])
+def test_multi_queue_graph_replay_histories(kind):
+    """The batched form at its configured shape -- 256 queues of capacity 2^e,
+    e uniform in 8..16 (seeded), one wavefront per 256 slots, 16 operations
+    per lane -- captured in a hipGraph with a history: after each of three
+    replays, with eager drains in between, every queue's history of that
+    replay passes O3/O4/O6 and yields a linearization witness (O10)."""
+    import paper_2606_01693_amd as gq
+    T = torch()
+    rng = np.random.default_rng(workloads.run_seed(5, 0))
+    caps = [int(2 ** e) for e in rng.integers(8, 17, size=256)]
+    lanes = [64 * max(1, c // 256) for c in caps]
+    lanes[int(np.argmax(caps))] += (-sum(lanes)) % 256
+    qs = [gq.Queue(kind, c, item_width=8, max_threads=l,
+                   **({"ymc_pool_cells": 16 * l * 16 + 4 * c} if kind == "ymc" else {}))
+          for c, l in zip(caps, lanes)]
+    print(f"[case] graph replay histories kind={kind} queues=256 lanes={sum(lanes)}", flush=True)
+    m = gq.Multi(qs, lanes, block=256)
+    ops = 16
+    total = sum(lanes)
+    counts = T.zeros(8 * len(qs), dtype=T.int64, device="cuda")
+    h = gq.History(total, ops)
+    s = T.cuda.Stream()
+    seed = workloads.run_seed(5, 2)
+    with T.cuda.stream(s):
+        m.capture(seed, ops, counts, s, hist=h)
+    s.synchronize()
+    lane0 = np.concatenate([[0], np.cumsum(lanes)])
+    prev = np.zeros((len(qs), 8), dtype=np.int64)
+    for rep in range(3):
+        with T.cuda.stream(s):
+            m.replay(s)
+        s.synchronize()
+        c = counts.cpu().numpy().reshape(-1, 8)
+        d = c - prev
+        prev = c.copy()
+        proc, op, st, val, call, ret, overflow = h.to_numpy()
+        assert overflow == 0
+        # replay r draws with seed + r + 1 (the captured seed bump)
+        assert np.array_equal(op, workloads.mix_roles(seed + rep + 1, total, ops).ravel())
+        for i, q in enumerate(qs):
+            assert q.check_error() == gq.GQ_OK, i
+            sel = (proc >= lane0[i]) & (proc < lane0[i + 1])
+            hist = oracle.History(proc[sel], op[sel], st[sel], val[sel], call[sel], ret[sel])
+            assert d[i, 0] == int(((hist.op == 0) & (hist.st == 0)).sum())
+            expect = int(d[i, 0] - d[i, 1])
+            drain = drain_fifo(q, caps[i] if kind != "ymc" else expect + 1)
+            assert len(drain) == expect, (rep, i)
+            rep_ = check_history(hist, drain, capacity=caps[i] if kind != "ymc" else 0)
+            assert_clean(rep_, hist, drain, tag=f"graph_{kind}_{rep}_{i}")
+    m.close()

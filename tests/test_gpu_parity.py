@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import workloads
-from tests.gpu_util import assert_clean, check_history, drain_fifo, history, torch, u64
+from tests.gpu_util import prefill, assert_clean, check_history, drain_fifo, history, torch, u64
 
 pytestmark = pytest.mark.gpu
 
@@ -32,23 +32,6 @@ def cap_of(kind, n):
 
 def all_zero(rep):
     return all(v == 0 for v in rep.values())
-
-
-def prefill(q, items):
-    T = torch()
-    if len(items) == 0:
-        return
-    t = T.tensor(np.asarray(items, dtype=np.uint64).view(np.int64), device="cuda")
-    # one lane enqueues them in list order
-    ops = T.zeros(len(items), dtype=T.uint8, device="cuda")
-    pauses = T.zeros(len(items), dtype=T.int16, device="cuda")
-    n_ops = T.tensor([len(items)], dtype=T.int32, device="cuda")
-    import paper_2606_01693_amd as gq
-    h = gq.History(1, len(items))
-    q.run_script(1, False, ops, t, pauses, n_ops, len(items), h)
-    T.cuda.synchronize()
-    _, _, s, _, _, _, _ = h.to_numpy()
-    assert (s == gq.GQ_OK).all()
 
 
 # ---------------------------------------------------------------------------

@@ -171,3 +171,48 @@ def test_serve_start_stop_without_jobs():
                    idle_timeout_ms=20000) as srv:
         r = srv.run([], np.zeros(0, dtype=np.int64))
         assert len(r["status"]) == 0
+
+
+@pytest.mark.parametrize("kind", ["lfq", "wfq"])
+def test_serve_mix_levels_elementwise_rmat12_20(kind):
+    """The serving workload at its configured graph sizes: R-MAT scales 12..20
+    (edge factor 16, one graph per scale), 120 jobs with Poisson arrivals
+    overlapping on 64 teams of 1024 lanes, every job writing its levels to its
+    own caller buffer.  Each job's levels equal the CPU BFS element by
+    element, in the mix and with each graph's job alone."""
+    import paper_2606_01693_amd as gq
+    T = torch()
+    seed = workloads.run_seed(5, 400)
+    pool = []
+    for i, scale in enumerate(range(12, 21)):
+        off, cols = workloads.rmat_graph(scale, 16, seed=seed + i)
+        root = workloads.bfs_root(off, seed + 31 * i)
+        exp, nl, _ = oracle.bfs(off, cols, root)
+        pool.append({"off": T.tensor(off.astype(np.int32), device="cuda"),
+                     "cols": T.tensor(cols.astype(np.int32), device="cuda"), "root": root,
+                     "exp": exp, "levels": nl, "nv": len(off) - 1})
+    T.cuda.synchronize()
+    rng = np.random.default_rng(seed + 1)
+    pick = rng.integers(0, len(pool), size=120)
+    arr = np.cumsum(rng.exponential(200_000, size=len(pick))).astype(np.int64)
+    outs = [T.full((pool[i]["nv"],), -7, dtype=T.int32, device="cuda") for i in pick]
+    reqs = [(pool[i]["off"], pool[i]["cols"], pool[i]["root"], o) for i, o in zip(pick, outs)]
+    print(f"[case] serve element-wise kind={kind} jobs={len(reqs)} scales 12..20", flush=True)
+    alone_outs = [T.full((p["nv"],), -7, dtype=T.int32, device="cuda") for p in pool]
+    # both runs back to back: the server ends itself after its idle timeout
+    with gq.Server(teams=64, team_lanes=1024, kind=kind, budget_bytes=8 << 30, ring_slots=256,
+                   idle_timeout_ms=30000) as srv:
+        mix = srv.run(reqs, arr)
+        alone = srv.run([(p["off"], p["cols"], p["root"], o) for p, o in zip(pool, alone_outs)],
+                        np.zeros(len(pool), dtype=np.int64), max_inflight=1)
+    T.cuda.synchronize()
+    assert (mix["status"] == 0).all(), mix["status"]
+    assert len(set(mix["team"].tolist())) > 1
+    for j, (i, o) in enumerate(zip(pick, outs)):
+        got = o.cpu().numpy().view(np.uint32)
+        diff = np.nonzero(got != pool[i]["exp"])[0]
+        assert len(diff) == 0, f"mixed job {j} (scale {12 + i}): {len(diff)} levels differ"
+        assert mix["levels"][j] == pool[i]["levels"]
+    assert (alone["status"] == 0).all()
+    for i, (p, o) in enumerate(zip(pool, alone_outs)):
+        assert np.array_equal(o.cpu().numpy().view(np.uint32), p["exp"]), f"scale {12 + i}"
