@@ -5,8 +5,12 @@ Two searches, each timing real launches on the current device with HIP events
 
 * ``tune_mix`` -- one queue under the mixed 50/50 workload at a fixed number of
   operation attempts: ticket group (64 = per-wavefront WaveFAA up to 1024 =
-  one FAA per workgroup), lane count (the workgroup count), slot layout and,
-  for G-WFQ / G-WFQ-YMC, patience.
+  one FAA per workgroup), lane count (the workgroup count), slot layout, ring
+  capacity (the workload's capacity times a factor, the items in flight
+  unchanged) and, for G-WFQ / G-WFQ-YMC, patience.  A configuration counts
+  only if its runs conserve the items: the kernel's multiset checksums of
+  what went in (prefill, enqueues) equal those of what came out (dequeues,
+  the drained remainder).
 * ``tune_multi`` -- the many-queue persistent launch: wavefronts given to each
   queue per 256 of its slots, with the work per queue fixed (4n operations in
   the 50/50 mix, the many-queue configuration), so more lanes means fewer
@@ -112,15 +116,17 @@ def _time_ms(torch, fn, reps: int) -> float:
 
 def tune_mix(kind: str, capacity: int, total_ops: int = 1 << 24,
              ticket_groups=(64, 256, 512, 1024), lanes_options=(1 << 17, 1 << 18, 1 << 19),
-             slot_modes=("linear", "remap"), patience_options=(None,), reps: int = 3,
+             slot_modes=("linear", "remap"), capacity_factors=(1, 2, 4),
+             patience_options=(None,), reps: int = 3,
              cache_path: str = "", force: bool = False,
              measure: Callable[[Dict], tuple] = None) -> TuneResult:
     """Fastest configuration for `total_ops` mixed 50/50 attempts on one queue
-    of `capacity` (uint64 items, prefilled to n/2)."""
-    key = f"mix/{_arch_or('any', measure)}/{kind}/cap{capacity}/ops{total_ops}"
-    cands = [dict(ticket_group=tg, lanes=l, slot_mode=sm, patience=p)
-             for tg, l, sm, p in itertools.product(ticket_groups, lanes_options, slot_modes,
-                                                   patience_options)
+    holding capacity/2 items (uint64), its ring `capacity` times a factor."""
+    key = (f"mix/{_arch_or('any', measure)}/{kind}/cap{capacity}/ops{total_ops}"
+           f"/f{'-'.join(str(f) for f in capacity_factors)}")
+    cands = [dict(ticket_group=tg, lanes=l, slot_mode=sm, capacity_factor=f, patience=p)
+             for tg, l, sm, f, p in itertools.product(ticket_groups, lanes_options, slot_modes,
+                                                      capacity_factors, patience_options)
              if total_ops % l == 0]
     if measure is None:
         measure = _mix_measure(kind, capacity, total_ops, reps)
@@ -131,15 +137,27 @@ def _arch_or(default: str, measure) -> str:
     return default if measure is not None else _device_arch()
 
 
+def checksums(v: np.ndarray):
+    """(count, wrapping sum of v, wrapping sum of v * v) of uint64 items."""
+    with np.errstate(over="ignore"):
+        return int(v.shape[0]), int(v.sum(dtype=np.uint64)), int((v * v).sum(dtype=np.uint64))
+
+
+def _csum_add(a, b):
+    m = (1 << 64) - 1
+    return a[0] + b[0], (a[1] + b[1]) & m, (a[2] + b[2]) & m
+
+
 def _mix_measure(kind, capacity, total_ops, reps):
     import torch
 
-    from . import Queue
+    from . import GQ_OK, Queue
 
     def run(c):
-        q = Queue(kind, capacity, item_width=8, max_threads=c["lanes"], slot_mode=c["slot_mode"],
+        ring = capacity * c.get("capacity_factor", 1)
+        q = Queue(kind, ring, item_width=8, max_threads=c["lanes"], slot_mode=c["slot_mode"],
                   ticket_group=c["ticket_group"], patience=c["patience"],
-                  ymc_pool_cells=(total_ops * (reps + 1) + capacity) if kind == "ymc" else 0)
+                  ymc_pool_cells=(total_ops * (reps + 1) + ring) if kind == "ymc" else 0)
         try:
             pre = torch.arange(1, capacity // 2 + 1, dtype=torch.int64, device="cuda")
             q.enqueue_batch(pre)
@@ -151,10 +169,25 @@ def _mix_measure(kind, capacity, total_ops, reps):
                 q.run_mix(seed[0], c["lanes"], total_ops // c["lanes"], counts)
 
             ms = _time_ms(torch, launch, reps)
-            cnt = counts.cpu().tolist()
+            cnt = counts.cpu().numpy().view(np.uint64).tolist()
             err = q.check_error()
             if err != 0:
                 raise RuntimeError(f"device error {err}")
+            # conservation over all launches: prefill + enqueued = dequeued + left
+            out = torch.zeros(ring, dtype=torch.int64, device="cuda")
+            st = torch.zeros(ring, dtype=torch.uint8, device="cuda")
+            left = []
+            while True:
+                q.dequeue_batch(out, st)
+                ok = st.cpu().numpy() == GQ_OK
+                if not ok.any():
+                    break
+                left.append(out.cpu().numpy().view(np.uint64)[ok])
+            left = np.concatenate(left) if left else np.zeros(0, dtype=np.uint64)
+            put = _csum_add(checksums(pre.cpu().numpy().view(np.uint64)), (cnt[0], cnt[6], cnt[7]))
+            got = _csum_add((cnt[1], cnt[4], cnt[5]), checksums(left))
+            if put != got:
+                raise RuntimeError(f"items not conserved: in {put}, out {got}")
             return ms, (cnt[0] + cnt[1]) / (reps + 1)
         finally:
             q.close()

@@ -12,6 +12,7 @@ def fake_mix(cand):
     ms = 10.0 / cand["ticket_group"] * (1 << 19) / cand["lanes"]
     if cand["slot_mode"] == "remap":
         ms *= 1.5
+    ms *= {1: 1.2, 2: 1.0, 4: 1.1}[cand.get("capacity_factor", 1)]
     return ms, 1 << 24
 
 
@@ -20,10 +21,10 @@ def test_tune_mix_picks_fastest_and_records_failures(tmp_path):
     path = str(tmp_path / "cache.json")
     r = at.tune_mix("lfq", 1 << 20, cache_path=path, measure=fake_mix)
     assert r.best == {"ticket_group": 1024, "lanes": 1 << 19, "slot_mode": "linear",
-                      "patience": None}
+                      "capacity_factor": 2, "patience": None}
     assert r.best_ms == min(t["ms"] for t in r.table if "ms" in t)
     assert any("error" in t for t in r.table)
-    assert len(r.table) == 4 * 3 * 2
+    assert len(r.table) == 4 * 3 * 2 * 3
     data = json.load(open(path))
     assert r.key in data and data[r.key]["best"] == r.best
 
@@ -51,7 +52,8 @@ def test_cache_hit_skips_measurement(tmp_path):
 def test_lane_options_must_divide_the_work():
     from paper_2606_01693_amd import autotune as at
     r = at.tune_mix("lfq", 1 << 10, total_ops=3 << 16, lanes_options=(1 << 17, 3 << 15),
-                    ticket_groups=(64,), slot_modes=("linear",), measure=fake_mix)
+                    ticket_groups=(64,), slot_modes=("linear",), capacity_factors=(1,),
+                    measure=fake_mix)
     assert [t["lanes"] for t in r.table] == [3 << 15]
 
 
@@ -102,3 +104,22 @@ def test_tune_prodcons_keeps_only_completed_runs(tmp_path):
     assert r.best == {"patience": [256, 1024], "help_delay": 16}
     assert sum("error" in t for t in r.table) == 3 and len(r.table) == 9
     assert at.cached(path, r.key).best == r.best
+
+
+def test_mix_conservation_checksums_match_oracle():
+    """The tuner's conservation check uses the same (count, S1, S2) the oracle
+    defines (sums of v and v * v modulo 2^64), and it tells apart a multiset
+    that lost one item and gained another of the same sum."""
+    import numpy as np
+
+    import oracle
+    from paper_2606_01693_amd import autotune as at
+    rng = np.random.default_rng(5)
+    v = rng.integers(0, 1 << 63, 1000, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+    assert at.checksums(v) == oracle.multiset_checksums(v)
+    w = v.copy()
+    w[0] += np.uint64(3)
+    w[1] -= np.uint64(3)  # same count, same S1
+    assert at.checksums(w)[:2] == at.checksums(v)[:2] and at.checksums(w) != at.checksums(v)
+    a, b = at.checksums(v[:400]), at.checksums(v[400:])
+    assert at._csum_add(a, b) == at.checksums(v)

@@ -5,14 +5,26 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("kind", ["lfq", "wfq", "ymc"])
+def test_tune_mix_conserves(kind):
+    """The conservation check passes for every queue kind on a real run."""
+    from paper_2606_01693_amd import autotune as at
+    r = at.tune_mix(kind, 1 << 12, total_ops=1 << 18, ticket_groups=(256,),
+                    lanes_options=(1 << 12,), slot_modes=("linear",), capacity_factors=(2,),
+                    reps=2)
+    assert all("mops" in t for t in r.table), r.table
+
+
 def test_tune_mix_small(tmp_path):
     from paper_2606_01693_amd import autotune as at
     path = str(tmp_path / "tune.json")
     r = at.tune_mix("lfq", 1 << 12, total_ops=1 << 18, ticket_groups=(64, 1024),
-                    lanes_options=(1 << 12, 1 << 13), slot_modes=("linear",), reps=2,
-                    cache_path=path)
+                    lanes_options=(1 << 12, 1 << 13), slot_modes=("linear",),
+                    capacity_factors=(1, 4), reps=2, cache_path=path)
     good = [t for t in r.table if "mops" in t]
-    assert len(good) == 4 and r.best_mops == max(t["mops"] for t in good)
+    # every configuration ran and conserved its items (a failed check is an "error" row)
+    assert len(good) == 8, [t for t in r.table if "error" in t]
+    assert r.best_mops == max(t["mops"] for t in good)
     assert at.cached(path, r.key).best == r.best
 
 
