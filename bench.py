@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 CAP = 1 << 20
 LANES = 2048 * 256
 OPS_PER_LANE = 128          # 2^26 attempts per step
+STEP_OPS = LANES * OPS_PER_LANE
 ITEM_BYTES = 8
 # Algorithmic bytes per successful operation of the outer queue's fast path:
 # two slot RMWs (8 B each, counted read + write), two slot loads, two
@@ -59,11 +60,11 @@ KERNEL_SOURCES = ("include/gq/common.h",
                   "include/gq.h", "include/gq_device.h")
 _PROFILE = "profiles/k_mix_group_mixed5050_cap2p20_ops2p26.md"
 TRAFFIC_PROFILE = {  # kind -> scaled FETCH_SIZE + WRITE_SIZE bytes per launch of the step kernel
-    "lfq": {"sources_sha256_16": "e78101372cd489fc", "bytes_per_launch": 4.009e9,
+    "lfq": {"sources_sha256_16": "08ce59664ff5b36f", "bytes_per_launch": 3.690e9,
             "profile": _PROFILE},
-    "wfq": {"sources_sha256_16": "e78101372cd489fc", "bytes_per_launch": 4.198e9,
+    "wfq": {"sources_sha256_16": "08ce59664ff5b36f", "bytes_per_launch": 3.831e9,
             "profile": _PROFILE},
-    "ymc": {"sources_sha256_16": "e78101372cd489fc", "bytes_per_launch": 3.098e9,
+    "ymc": {"sources_sha256_16": "08ce59664ff5b36f", "bytes_per_launch": 3.031e9,
             "profile": _PROFILE},
 }
 NAMES = {"lfq": "G-LFQ", "wfq": "G-WFQ", "ymc": "G-WFQ-YMC"}
@@ -73,14 +74,14 @@ NAMES = {"lfq": "G-LFQ", "wfq": "G-WFQ", "ymc": "G-WFQ-YMC"}
 # same conditions as the traffic figure.
 _COUNTERS = "profiles/k_mix_group_mixed5050_sq_tcc_counters.md"
 COUNTER_PROFILE = {
-    "lfq": {"valu_per_op": 3.08, "wait_frac": 0.781, "wait_per_op": 1.16e-8,
-            "tcc_atomic_per_op": 0.571},
-    "wfq": {"valu_per_op": 6.44, "wait_frac": 0.763, "wait_per_op": 1.14e-8,
-            "tcc_atomic_per_op": 0.571},
-    "ymc": {"valu_per_op": 1.87, "wait_frac": 0.875, "wait_per_op": 1.30e-8,
+    "lfq": {"valu_per_op": 3.85, "wait_frac": 0.826, "wait_per_op": 1.23e-8,
+            "tcc_atomic_per_op": 0.531},
+    "wfq": {"valu_per_op": 6.22, "wait_frac": 0.765, "wait_per_op": 1.14e-8,
+            "tcc_atomic_per_op": 0.529},
+    "ymc": {"valu_per_op": 2.47, "wait_frac": 0.863, "wait_per_op": 1.29e-8,
             "tcc_atomic_per_op": 0.276},
 }
-COUNTER_SOURCES_HASH = "e78101372cd489fc"
+COUNTER_SOURCES_HASH = "08ce59664ff5b36f"
 
 
 def kernel_sources_hash() -> str:
@@ -142,12 +143,12 @@ def measure_probes(gq, torch):
     return res
 
 
-def cpu_baselines(seed, sample_lanes):
-    """Oracle replay (1 core) on a bounded sample of the same op stream, and
-    the host locked queue on all host cores."""
+def cpu_baselines(seed, sample_lanes, ops_per_lane=OPS_PER_LANE):
+    """Oracle replay (1 core) of the headline step's op stream (its lanes x
+    ops draws), and the host locked queue on all host cores."""
     import oracle
     import workloads
-    roles = workloads.mix_roles(seed, sample_lanes, OPS_PER_LANE)
+    roles = workloads.mix_roles(seed, sample_lanes, ops_per_lane)
     toks = workloads.mix_tokens(roles)
     pre = np.arange(1, CAP // 2 + 1, dtype=np.uint64) | np.uint64(0xFFFFFFFF << 32)
     t0 = time.perf_counter()
@@ -155,7 +156,7 @@ def cpu_baselines(seed, sample_lanes):
     dt = time.perf_counter() - t0
     ok = int((st == 0).sum())
     replay = {"value": ok / dt / 1e6, "unit": "Mops/s", "cores": 1, "kind": "oracle",
-              "sample": f"sequential FIFO replay of {sample_lanes} lanes x {OPS_PER_LANE} ops "
+              "sample": f"sequential FIFO replay of {sample_lanes} lanes x {ops_per_lane} ops "
                         f"of the same 50/50 stream in lane-major order, capacity 2^20, "
                         f"prefill n/2 ({roles.size} ops, {dt:.2f} s)"}
     cores = os.cpu_count() or 1
@@ -707,11 +708,27 @@ def step_plan(steps: int, warmup: int) -> dict:
             "fits": need <= YMC_STEP_POOL}
 
 
-def launch_desc(ticket_group: int) -> str:
+def step_shape(gq, kind: str, ticket_group: int):
+    """(lanes, ops per lane) of a variant's step: 2^26 attempts by the largest
+    power-of-two number of lanes, at most 2^19, that the device holds at once
+    in the group kernel's workgroups (one round of workgroups, none waiting
+    for another to finish).  The per-wavefront form (ticket group 64) keeps
+    2^19 lanes in workgroups of 256."""
     g = ticket_group or 1024
     if g <= 64:
-        return f"{LANES // 256} WGs x 256 lanes, per-wavefront ticket FAAs"
-    return f"{LANES // g} WGs x {g} lanes, one ticket FAA per counter per WG"
+        return LANES, OPS_PER_LANE
+    resident = gq.resident_blocks("mix_group", kind, g) * g
+    lanes = LANES
+    while lanes > g and lanes > resident:
+        lanes //= 2
+    return lanes, STEP_OPS // lanes
+
+
+def launch_desc(ticket_group: int, lanes: int = LANES) -> str:
+    g = ticket_group or 1024
+    if g <= 64:
+        return f"{lanes // 256} WGs x 256 lanes, per-wavefront ticket FAAs"
+    return f"{lanes // g} WGs x {g} lanes, one ticket FAA per counter per WG"
 
 
 def checksums(v: np.ndarray):
@@ -732,7 +749,8 @@ def run_variant(gq, torch, kind, args, base_seed):
     events on the launch stream), then drain what is left (untimed) and check
     conservation of the step with the kernel's multiset checksums: prefill +
     enqueued = dequeued + drained (counts and wrapping sums of v and v*v)."""
-    q = gq.Queue(kind, CAP, item_width=ITEM_BYTES, max_threads=LANES,
+    lanes, ops = step_shape(gq, kind, args.ticket_group)
+    q = gq.Queue(kind, CAP, item_width=ITEM_BYTES, max_threads=lanes,
                  slot_mode=args.slot_mode, fenced=args.fenced,
                  ymc_pool_cells=YMC_STEP_POOL if kind == "ymc" else 0,
                  ticket_group=args.ticket_group)
@@ -752,7 +770,7 @@ def run_variant(gq, torch, kind, args, base_seed):
             e0, e1 = _events(torch)
             t0 = time.perf_counter()
             e0.record()
-            q.run_mix(base_seed + i, LANES, OPS_PER_LANE, counts)
+            q.run_mix(base_seed + i, lanes, ops, counts)
             e1.record()
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -763,7 +781,7 @@ def run_variant(gq, torch, kind, args, base_seed):
             left = out.cpu().numpy().view(np.uint64)[st == gq.GQ_OK]
             put = csum_add(pre_sums, (c[0], c[6], c[7]))
             got = csum_add((c[1], c[4], c[5]), checksums(left))
-            ok_step = put == got and c[0] + c[1] + c[2] + c[3] == LANES * OPS_PER_LANE
+            ok_step = put == got and c[0] + c[1] + c[2] + c[3] == STEP_OPS
             conserved &= ok_step
             if i >= args.warmup:
                 kms.append(e0.elapsed_time(e1))
@@ -776,8 +794,11 @@ def run_variant(gq, torch, kind, args, base_seed):
         res = {
             "name": NAMES[kind],
             "kernel": (f"k_mix<{NAMES[kind]}>" if (args.ticket_group or 1024) <= 64
+                       else "k_mix_group_lfq" if kind == "lfq"
                        else f"k_mix_group<{NAMES[kind]}>"),
-            "launch": launch_desc(args.ticket_group),
+            "launch": launch_desc(args.ticket_group, lanes),
+            "lanes": lanes,
+            "ops_per_lane": ops,
             "mops": sum(oks) / (walls_a.sum() * 1e-3) / 1e6,
             "mops_kernel": ok_mean / (float(np.median(kms_a)) * 1e-3) / 1e6,
             "ok_ops_per_step": ok_mean,
@@ -877,11 +898,14 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{NAMES[head]}: mixed 50/50 enqueue/dequeue, capacity 2^20, uint64 "
-                        f"payload, 2^26 op attempts per step by 2^19 lanes x 128 ops "
-                        f"({launch_desc(args.ticket_group)}), queue reset and prefilled to n/2 "
+                        f"payload, 2^26 op attempts per step by {hv.get('lanes', LANES)} lanes x "
+                        f"{hv.get('ops_per_lane', OPS_PER_LANE)} ops "
+                        f"({hv.get('launch', launch_desc(args.ticket_group))}; the most lanes, up "
+                        f"to 2^19, resident at once), queue reset and prefilled to n/2 "
                         f"before each step (untimed); slots={args.slot_mode}, hand-off="
                         + ("fenced" if args.fenced else "atomic"),
-            "queue": NAMES[head], "capacity": CAP, "lanes": LANES, "ops_per_lane": OPS_PER_LANE,
+            "queue": NAMES[head], "capacity": CAP, "lanes": hv.get("lanes", LANES),
+            "ops_per_lane": hv.get("ops_per_lane", OPS_PER_LANE),
             "parallelism": "single GPU",
         },
         "step_plan": plan,
@@ -965,7 +989,9 @@ def main():
         section(out, "raytrace", lambda: bench_rt(gq, torch))
     if not args.no_cpu:
         def cpu():
-            replay, locked = cpu_baselines(base_seed, LANES)
+            hv = out["variants"].get(head, {})
+            replay, locked = cpu_baselines(base_seed, hv.get("lanes", LANES),
+                                           hv.get("ops_per_lane", OPS_PER_LANE))
             out["cpu_baseline"] = replay
             out["host"] = {"cpu": platform.processor() or platform.machine(),
                            "cores": os.cpu_count()}

@@ -214,7 +214,9 @@ gq_status gq_probe_fence(uint64_t *d_lines, uint32_t lanes, uint32_t iters, uint
                          void *stream);
 
 /* Number of workgroups of `block` lanes that can be resident at once for the
- * given driver kernel ("mix", "prodcons"), summed over all compute units.     */
+ * given driver kernel, summed over all compute units: "mix" (gq_run_mix's
+ * per-wavefront form), "mix_group" (its workgroup-ticket form, the kernel
+ * gq_run_mix launches when the ticket group exceeds 64), "prodcons".          */
 gq_status gq_resident_blocks(const char *kernel, gq_kind kind, uint32_t block,
                              uint32_t *out_blocks);
 

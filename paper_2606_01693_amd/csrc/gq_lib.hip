@@ -1394,7 +1394,8 @@ gq_status gq_probe_fence(uint64_t* d_lines, uint32_t lanes, uint32_t iters, uint
 template <int KIND>
 static const void* driver_fn(const char* kernel) {
   if (!strcmp(kernel, "mix")) return (const void*)k_mix<KIND, false>;
-  if (!strcmp(kernel, "mix_group")) return (const void*)k_mix_group<KIND, false>;
+  if (!strcmp(kernel, "mix_group"))  // the kernel launch_mix starts for the group form
+    return KIND == GQ_LFQ ? (const void*)k_mix_group_lfq<false> : (const void*)k_mix_group<KIND, false>;
   if (!strcmp(kernel, "prodcons")) return (const void*)k_prodcons<KIND, false>;
   return nullptr;
 }

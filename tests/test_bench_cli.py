@@ -53,3 +53,29 @@ def test_checksums_of_a_split_multiset_add_up():
     w = v.copy()
     w[5] = w[6]
     assert bench.checksums(w) != bench.checksums(v)
+
+
+def test_step_shape_follows_residency():
+    """A variant's step uses the most lanes, up to 2^19 and a power of two,
+    that the device holds at once in 1024-lane workgroups; the work per step
+    stays 2^26 attempts.  The per-wavefront form keeps 2^19 lanes."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    class FakeGq:
+        def __init__(self, blocks):
+            self.blocks = blocks
+
+        def resident_blocks(self, kernel, kind, block):
+            assert kernel == "mix_group" and block == 1024
+            return self.blocks[kind]
+
+    g = FakeGq({"lfq": 512, "wfq": 256, "ymc": 300})
+    assert bench.step_shape(g, "lfq", 0) == (1 << 19, 128)
+    assert bench.step_shape(g, "wfq", 1024) == (1 << 18, 256)
+    assert bench.step_shape(g, "ymc", 0) == (1 << 18, 256)  # 300 blocks: 2^18 is the largest power
+    assert bench.step_shape(FakeGq({"lfq": 4096}), "lfq", 0) == (1 << 19, 128)
+    assert bench.step_shape(g, "wfq", 64) == (1 << 19, 128)
+    for kind in ("lfq", "wfq", "ymc"):
+        lanes, ops = bench.step_shape(g, kind, 0)
+        assert lanes * ops == 1 << 26

@@ -344,7 +344,8 @@ def checksum_add(a, b):
 @pytest.mark.parametrize("tg", TICKET_GROUPS)
 def test_mix_timed_kernel_conserves(kind, tg):
     """The kernel the benchmark times, in the benchmark's own launch: no
-    history, atomic hand-off, capacity 2^20, 2048 x 256 lanes x 128 ops (2^26),
+    history, atomic hand-off, capacity 2^20, 2^26 attempts by the lanes the
+    benchmark's step uses (the most lanes, up to 2^19, resident at once),
     prefill n/2.  O3 conservation at full size: the tokens the lanes enqueued
     (from their per-lane enqueue counts) and the prefill must equal, as a
     multiset, what the lanes dequeued plus what a sequential drain finds left
@@ -354,7 +355,10 @@ def test_mix_timed_kernel_conserves(kind, tg):
     increasing order (a FIFO's remainder)."""
     import paper_2606_01693_amd as gq
     T = torch()
-    n, lanes, ops = 1 << 20, 2048 * 256, 128
+    import bench
+    n = 1 << 20
+    lanes, ops = bench.step_shape(gq, kind, tg)
+    assert lanes * ops == 1 << 26
     seed = workloads.run_seed(2, 1)
     q = make_queue(kind, n, lanes=lanes, ticket_group=tg,
                    **({"ymc_pool_cells": 1 << 27} if kind == "ymc" else {}))
