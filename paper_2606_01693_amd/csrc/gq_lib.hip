@@ -442,7 +442,56 @@ struct MixTally {
     wave_add(counts + 7, s2e);
     wave_add(stats + S_CAS_FAIL, cf);
   }
+  // The same sums for a whole workgroup, whose lanes all arrive here
+  // together: each wavefront's total goes into the workgroup's `acc` words
+  // (LDS, zeroed at kernel start), then one lane per counter adds it to the
+  // device word.  With one device atomic per wavefront and counter, the
+  // thousands of wavefronts of a launch ending together queued on the same
+  // few words (one L2 line) for a tenth of a G-WFQ launch.
+  __device__ __forceinline__ void flush_group(uint64_t* counts, uint64_t* stats, uint64_t g,
+                                              uint64_t* acc) const {
+    uint64_t s1e, s2e;
+    token_sums(g, ok_e, s1e, s2e);
+    const uint64_t v[9] = {ok_e, ok_d, full, empty, s1d, s2d, s1e, s2e, cf};
+    const bool lead = (threadIdx.x & 63) == 0;
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+      const uint64_t w = wave_sum(v[i]);
+      if (lead && w) atomicAdd((unsigned long long*)&acc[i], (unsigned long long)w);
+    }
+    __syncthreads();
+    if (threadIdx.x < 9 && acc[threadIdx.x])
+      faa(threadIdx.x < 8 ? counts + threadIdx.x : stats + S_CAS_FAIL, acc[threadIdx.x]);
+  }
 };
+
+// The queue's device view with every control word addressed from one base.
+// The control words sit at fixed offsets of the queue's allocation (OFF_*),
+// so the compiler can reach them all as base + immediate offset instead of
+// holding a 64-bit address per word in scalar registers: G-WFQ's group
+// kernel otherwise needs more scalar registers than a wavefront has, parks
+// the overflow in vector-register lanes and reloads it with VALU
+// instructions on every operation.  LIN pins the linear slot layout (the
+// caller checks that the queue uses it), which removes the layout branches
+// from every slot access.  Valid for queues made by gq_create only.
+template <int KIND, bool LIN>
+__device__ __forceinline__ gq_dev kernel_view(const gq_dev& q) {
+  gq_dev l = q;
+  uint8_t* base = (uint8_t*)q.err - OFF_ERR;
+  l.aq.head = (uint64_t*)(base + OFF_AQ_HEAD);
+  l.aq.tail = (uint64_t*)(base + OFF_AQ_TAIL);
+  l.aq.threshold = (int64_t*)(base + OFF_AQ_THR);
+  l.fq.head = (uint64_t*)(base + OFF_FQ_HEAD);
+  l.fq.tail = (uint64_t*)(base + OFF_FQ_TAIL);
+  l.fq.threshold = (int64_t*)(base + OFF_FQ_THR);
+  l.stats = (uint64_t*)(base + OFF_STATS);
+  if (KIND == GQ_WFQ) {
+    l.aq.announce = (uint64_t*)(base + OFF_AQ_ANN);
+    l.fq.announce = (uint64_t*)(base + OFF_FQ_ANN);
+  }
+  if (LIN) l.slot_mode = GQ_SLOTS_LINEAR;
+  return l;
+}
 
 template <int KIND, bool REC>
 __device__ __forceinline__ void mix_lane(const gq_dev& q, uint64_t g, uint32_t tid, uint64_t seed,
@@ -482,10 +531,11 @@ __global__ __launch_bounds__(256) void k_mix(gq_dev q, uint64_t seed, uint32_t o
 // the workgroup performs its op r together with the others (group_op), so
 // each ticket counter sees one FAA per workgroup per phase.  Same draws,
 // tokens and counts as k_mix.
-template <int KIND, bool REC>
-__device__ __forceinline__ void mix_group_body(const gq_dev& q, uint64_t seed, uint32_t ops,
+template <int KIND, bool REC, bool LIN>
+__device__ __forceinline__ void mix_group_body(const gq_dev& q0, uint64_t seed, uint32_t ops,
                                                uint64_t* counts, uint32_t* lane_enq,
-                                               const Rec& rec, GroupLds& lds) {
+                                               const Rec& rec, GroupLds& lds, uint64_t* acc) {
+  const gq_dev q = kernel_view<KIND, LIN>(q0);
   uint32_t par = 0;
   const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   // per-lane counts never exceed `ops` (< 2^32): 32-bit registers suffice
@@ -506,14 +556,17 @@ __device__ __forceinline__ void mix_group_body(const gq_dev& q, uint64_t seed, u
   }
   if (REC && rec.h.count) rec.h.count[g] = ops;
   if (lane_enq) lane_enq[g] = t.ok_e;
-  t.flush(counts, q.stats, g);
+  t.flush_group(counts, q.stats, g, acc);
 }
 
-template <int KIND, bool REC>
+template <int KIND, bool REC, bool LIN>
 __global__ __launch_bounds__(1024) void k_mix_group(gq_dev q, uint64_t seed, uint32_t ops,
                                                     uint64_t* counts, uint32_t* lane_enq, Rec rec) {
   __shared__ GroupLds lds;
-  mix_group_body<KIND, REC>(q, seed, ops, counts, lane_enq, rec, lds);
+  __shared__ uint64_t acc[9];
+  if (threadIdx.x < 9) acc[threadIdx.x] = 0;
+  __syncthreads();
+  mix_group_body<KIND, REC, LIN>(q, seed, ops, counts, lane_enq, rec, lds, acc);
 }
 
 // G-LFQ's copy of the group kernel, compiled for 8 wavefronts per SIMD (at
@@ -522,11 +575,14 @@ __global__ __launch_bounds__(1024) void k_mix_group(gq_dev q, uint64_t seed, uin
 // of in two rounds of workgroups (measured 2.41 -> 2.21 ms per 2^26 ops).
 // G-WFQ and G-WFQ-YMC need 100-123 VGPRs; capped, their spills cost more than
 // the second round of workgroups (2.74 -> 3.32 ms and 2.14 -> 2.53 ms).
-template <bool REC>
+template <bool REC, bool LIN>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_mix_group_lfq(
     gq_dev q, uint64_t seed, uint32_t ops, uint64_t* counts, uint32_t* lane_enq, Rec rec) {
   __shared__ GroupLds lds;
-  mix_group_body<GQ_LFQ, REC>(q, seed, ops, counts, lane_enq, rec, lds);
+  __shared__ uint64_t acc[9];
+  if (threadIdx.x < 9) acc[threadIdx.x] = 0;
+  __syncthreads();
+  mix_group_body<GQ_LFQ, REC, LIN>(q, seed, ops, counts, lane_enq, rec, lds, acc);
 }
 
 // Many independent queues in one launch: wavefront w works on queue
@@ -1157,7 +1213,7 @@ template <int KIND>
 static uint32_t mix_shape(const gq_queue* q, uint32_t lanes, bool hist, const void** fn) {
   const uint32_t gb = group_block(q, lanes);
   if (gb > 64) {
-    *fn = hist ? (const void*)k_mix_group<KIND, true> : (const void*)k_mix_group<KIND, false>;
+    *fn = hist ? (const void*)k_mix_group<KIND, true, false> : (const void*)k_mix_group<KIND, false, false>;
     return gb;
   }
   *fn = hist ? (const void*)k_mix<KIND, true> : (const void*)k_mix<KIND, false>;
@@ -1171,16 +1227,23 @@ static void launch_mix(gq_queue* q, uint64_t seed, uint32_t lanes, uint32_t ops,
   const void* fn = nullptr;
   const uint32_t b = mix_shape<KIND>(q, lanes, hist != nullptr, &fn);
   const dim3 grid(lanes / b), block(b);
-  if (fn == (const void*)k_mix_group<KIND, true> || fn == (const void*)k_mix_group<KIND, false>) {
+  if (fn == (const void*)k_mix_group<KIND, true, false> ||
+      fn == (const void*)k_mix_group<KIND, false, false>) {
+    // the timed form (no history) has a copy for linear slots, the default
+    const bool lin = !hist && q->dev.slot_mode == GQ_SLOTS_LINEAR;
     if (KIND == GQ_LFQ) {
       if (hist)
-        LAUNCH((k_mix_group_lfq<true>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
+        LAUNCH((k_mix_group_lfq<true, false>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
+      else if (lin)
+        LAUNCH((k_mix_group_lfq<false, true>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
       else
-        LAUNCH((k_mix_group_lfq<false>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
+        LAUNCH((k_mix_group_lfq<false, false>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
     } else if (hist) {
-      LAUNCH((k_mix_group<KIND, true>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
+      LAUNCH((k_mix_group<KIND, true, false>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
+    } else if (lin) {
+      LAUNCH((k_mix_group<KIND, false, true>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
     } else {
-      LAUNCH((k_mix_group<KIND, false>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
+      LAUNCH((k_mix_group<KIND, false, false>), grid, block, 0, s, q->dev, seed, ops, counts, lane_enq, rec);
     }
     return;
   }
@@ -1395,7 +1458,8 @@ template <int KIND>
 static const void* driver_fn(const char* kernel) {
   if (!strcmp(kernel, "mix")) return (const void*)k_mix<KIND, false>;
   if (!strcmp(kernel, "mix_group"))  // the kernel launch_mix starts for the group form
-    return KIND == GQ_LFQ ? (const void*)k_mix_group_lfq<false> : (const void*)k_mix_group<KIND, false>;
+    return KIND == GQ_LFQ ? (const void*)k_mix_group_lfq<false, true>
+                          : (const void*)k_mix_group<KIND, false, true>;
   if (!strcmp(kernel, "prodcons")) return (const void*)k_prodcons<KIND, false>;
   return nullptr;
 }

@@ -387,6 +387,36 @@ def test_mix_timed_kernel_conserves(kind, tg):
     assert oracle.producer_order(dh)["consumer_order"] == 0
 
 
+@pytest.mark.parametrize("kind", ["lfq", "wfq"])
+@pytest.mark.parametrize("slot_mode", ["remap", "padded", "linear"])
+def test_mix_group_kernel_conserves_every_layout(kind, slot_mode):
+    """The group kernel without a history has a copy specialised for linear
+    slots; both copies conserve the items on every slot layout: capacity
+    2^16 prefilled to n/2, 2^14 lanes x 64 ops in 1024-lane workgroups, the
+    prefill plus the enqueued tokens equal (checksums) the dequeued items
+    plus the drain, and the kernel's enqueue checksums equal the oracle's
+    over the tokens its per-lane counts name."""
+    import paper_2606_01693_amd as gq
+    T = torch()
+    n, lanes, ops = 1 << 16, 1 << 14, 64
+    q = make_queue(kind, n, lanes=lanes, slot_mode=slot_mode, ticket_group=1024)
+    pre = np.array([int(workloads.token(0xFFFFFFFF, i)) for i in range(n // 2)], dtype=np.uint64)
+    q.enqueue_batch(T.tensor(pre.view(np.int64), device="cuda"))
+    counts = T.zeros(8, dtype=T.int64, device="cuda")
+    lane_enq = T.zeros(lanes, dtype=T.int32, device="cuda")
+    q.run_mix(workloads.run_seed(2, 7), lanes, ops, counts, lane_enq=lane_enq)
+    T.cuda.synchronize()
+    assert q.check_error() == gq.GQ_OK
+    c = counts.cpu().numpy().view(np.uint64).tolist()
+    enq = oracle.mix_tokens_from_counts(lane_enq.cpu().numpy())
+    assert oracle.multiset_checksums(enq) == (c[0], c[6], c[7])
+    assert c[0] + c[1] + c[2] + c[3] == lanes * ops
+    drain = drain_fifo(q, n)
+    put = checksum_add(oracle.multiset_checksums(pre), oracle.multiset_checksums(enq))
+    out = checksum_add((c[1], c[4], c[5]), oracle.multiset_checksums(drain))
+    assert put == out, (put, out)
+
+
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("tg", TICKET_GROUPS)
 def test_mix_full_size(kind, tg):
