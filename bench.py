@@ -60,11 +60,11 @@ KERNEL_SOURCES = ("include/gq/common.h",
                   "include/gq.h", "include/gq_device.h")
 _PROFILE = "profiles/k_mix_group_mixed5050_cap2p20_ops2p26.md"
 TRAFFIC_PROFILE = {  # kind -> scaled FETCH_SIZE + WRITE_SIZE bytes per launch of the step kernel
-    "lfq": {"sources_sha256_16": "e1d80deb9b21a339", "bytes_per_launch": 3.690e9,
+    "lfq": {"sources_sha256_16": "455ae1817f89c0e2", "bytes_per_launch": 3.691e9,
             "profile": _PROFILE},
-    "wfq": {"sources_sha256_16": "e1d80deb9b21a339", "bytes_per_launch": 3.832e9,
+    "wfq": {"sources_sha256_16": "455ae1817f89c0e2", "bytes_per_launch": 3.800e9,
             "profile": _PROFILE},
-    "ymc": {"sources_sha256_16": "e1d80deb9b21a339", "bytes_per_launch": 3.039e9,
+    "ymc": {"sources_sha256_16": "455ae1817f89c0e2", "bytes_per_launch": 3.063e9,
             "profile": _PROFILE},
 }
 NAMES = {"lfq": "G-LFQ", "wfq": "G-WFQ", "ymc": "G-WFQ-YMC"}
@@ -76,12 +76,12 @@ _COUNTERS = "profiles/k_mix_group_mixed5050_sq_tcc_counters.md"
 COUNTER_PROFILE = {
     "lfq": {"valu_per_op": 3.22, "wait_frac": 0.839, "wait_per_op": 1.25e-8,
             "tcc_atomic_per_op": 0.531},
-    "wfq": {"valu_per_op": 5.67, "wait_frac": 0.771, "wait_per_op": 1.15e-8,
+    "wfq": {"valu_per_op": 5.31, "wait_frac": 0.773, "wait_per_op": 1.15e-8,
             "tcc_atomic_per_op": 0.529},
     "ymc": {"valu_per_op": 2.34, "wait_frac": 0.862, "wait_per_op": 1.28e-8,
             "tcc_atomic_per_op": 0.275},
 }
-COUNTER_SOURCES_HASH = "e1d80deb9b21a339"
+COUNTER_SOURCES_HASH = "455ae1817f89c0e2"
 
 
 def kernel_sources_hash() -> str:

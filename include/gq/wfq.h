@@ -514,11 +514,11 @@ __device__ __forceinline__ void help_announced(const WRing& r, uint32_t tid) {
 }
 
 // Every D operations of a lane, inspect one peer's records on both rings.
-// The lane's counter and next peer live in one 32-bit word of a compact
-// per-lane array (a wavefront's 64 words share 2 lines).
-__device__ __forceinline__ void help_check(const gq_dev& q, uint32_t tid) {
-  uint32_t* hp = q.help_ctr + tid;
-  const uint32_t h = *hp;  // owner-private
+// The lane's counter and next peer form one 32-bit word <peer:20 | count:12>
+// (help step state).  help_step advances it in a register; help_check keeps
+// it in the queue's compact per-lane array (a wavefront's 64 words share 2
+// lines) for callers that hold no state between operations.
+__device__ __forceinline__ void help_step(const gq_dev& q, uint32_t tid, uint32_t& h) {
   uint32_t cnt = (h & 0xFFFu) + 1;
   uint32_t peer = h >> 12;
   if (cnt >= q.help_delay) {
@@ -530,7 +530,25 @@ __device__ __forceinline__ void help_check(const gq_dev& q, uint32_t tid) {
     }
     peer = peer + 1 >= q.max_threads ? 0 : peer + 1;
   }
-  *hp = (peer << 12) | cnt;
+  h = (peer << 12) | cnt;
+}
+
+__device__ __forceinline__ void help_check(const gq_dev& q, uint32_t tid) {
+  uint32_t* hp = q.help_ctr + tid;
+  uint32_t h = *hp;  // owner-private
+  help_step(q, tid, h);
+  *hp = h;
+}
+
+// The help step state of lane tid, to hold in a register across a run of
+// group_op calls that pass it (help_load before the first, help_store after
+// the last): each operation then saves the array's load and store, whose
+// load would otherwise sit on the operation's dependency chain.
+__device__ __forceinline__ uint32_t help_load(const gq_dev& q, uint32_t tid) {
+  return q.help_ctr[tid];
+}
+__device__ __forceinline__ void help_store(const gq_dev& q, uint32_t tid, uint32_t h) {
+  q.help_ctr[tid] = h;
 }
 
 // Inner enqueue of idx: fast path up to patience_enq attempts, then the slow path.
@@ -696,14 +714,17 @@ __device__ __forceinline__ uint64_t group_decode(uint64_t word) {
 template <bool FENCED>
 __device__ __forceinline__ int group_op_impl(const gq_dev& q, int role, uint64_t& item,
                                              uint32_t tid, uint32_t& cf, GroupLds& s,
-                                             uint32_t& par) {
+                                             uint32_t& par, uint32_t* help) {
   int st = role == ROLE_ENQ ? GQ_FULL : role == ROLE_DEQ ? GQ_EMPTY : GQ_OK;
   if (role != ROLE_NONE && tid >= q.max_threads) {
     latch_error(q.err, (uint64_t)(-GQ_ERR_INVALID));
     st = GQ_ERR_INVALID;
     role = ROLE_NONE;
   }
-  if (role != ROLE_NONE) help_check(q, tid);
+  if (role != ROLE_NONE) {
+    if (help) help_step(q, tid, *help);
+    else help_check(q, tid);
+  }
   const WRing fq = make_wring(q.fq, q);
   const WRing aq = make_wring(q.aq, q);
   const bool wf = role == ROLE_ENQ && ld(fq.g.thr) >= 0;
@@ -736,10 +757,13 @@ __device__ __forceinline__ int group_op_impl(const gq_dev& q, int role, uint64_t
   return st;
 }
 
+// `help`: the lane's help step state held by the caller (help_load /
+// help_store), or nullptr to keep it in the queue's per-lane array.
 __device__ __forceinline__ int group_op(const gq_dev& q, int role, uint64_t& item, uint32_t tid,
-                                        uint32_t& cf, GroupLds& s, uint32_t& par) {
-  return (q.flags & GQ_OPT_FENCED) ? group_op_impl<true>(q, role, item, tid, cf, s, par)
-                                   : group_op_impl<false>(q, role, item, tid, cf, s, par);
+                                        uint32_t& cf, GroupLds& s, uint32_t& par,
+                                        uint32_t* help = nullptr) {
+  return (q.flags & GQ_OPT_FENCED) ? group_op_impl<true>(q, role, item, tid, cf, s, par, help)
+                                   : group_op_impl<false>(q, role, item, tid, cf, s, par, help);
 }
 
 __device__ __forceinline__ int enqueue(const gq_dev& q, uint64_t item, uint32_t tid, uint32_t& cf) {

@@ -71,19 +71,25 @@ __device__ __forceinline__ int gq_dequeue_k(const gq_dev& q, uint64_t* item, uin
  * whole workgroup (Lemma 1's aggregation at workgroup scale); the operation
  * is otherwise the same linearizable enqueue or dequeue as above.  `lds` is
  * one __shared__ gq::GroupLds per workgroup and `par` a per-thread word that
- * starts at 0 and is passed to every call.  Returns the lane's status
+ * starts at 0 and is passed to every call.  `help` (G-WFQ; optional): the
+ * lane's help step state held in a register across calls -- load it with
+ * gq::wfq::help_load(q, tid) before the first call and store it back with
+ * gq::wfq::help_store(q, tid, h) after the last; without it each operation
+ * reads and writes the queue's per-lane copy.  Returns the lane's status
  * (GQ_OK for ROLE_NONE).  Contains barriers: never call it from divergent
  * code.                                                                      */
 template <int KIND>
 __device__ __forceinline__ int gq_group_op_k(const gq_dev& q, int role, uint64_t& item,
                                              uint32_t tid, uint32_t& cas_fail, gq::GroupLds& lds,
-                                             uint32_t& par) {
+                                             uint32_t& par, uint32_t* help = nullptr) {
   if constexpr (KIND == GQ_LFQ) {
     (void)tid;
+    (void)help;
     return gq::lfq::group_op(q, role, item, cas_fail, lds, par);
   } else if constexpr (KIND == GQ_WFQ) {
-    return gq::wfq::group_op(q, role, item, tid, cas_fail, lds, par);
+    return gq::wfq::group_op(q, role, item, tid, cas_fail, lds, par, help);
   } else {
+    (void)help;
     return gq::ymc::group_op(q, role, item, tid, cas_fail, lds, par);
   }
 }

@@ -204,8 +204,14 @@ __device__ void init_wfq_range(const gq_dev& q, uint64_t g0, uint64_t stride) {
       st(&R->req, 0ull);
       st(&R->next_seq, 1ull);
     }
+    // The lanes of a wavefront share one phase of the help step (count
+    // (t / 64) mod D; wavefronts are staggered): together they inspect 64
+    // peers once every D operations, their loads in flight at once.  With
+    // a phase per lane, one lane of every wavefront would run the help
+    // step on every operation, and its load of a peer's request word would
+    // stand in every operation's dependency chain.
     const uint32_t peer = (uint32_t)((t + 1) % q.max_threads);
-    st(q.help_ctr + t, (peer << 12) | (uint32_t)(t % (q.help_delay ? q.help_delay : 1)));
+    st(q.help_ctr + t, (peer << 12) | (uint32_t)((t / 64) % (q.help_delay ? q.help_delay : 1)));
     q.aq.hint[t] = 0;
     q.fq.hint[t] = 0;
   }
@@ -538,6 +544,9 @@ __device__ __forceinline__ void mix_group_body(const gq_dev& q0, uint64_t seed, 
   const gq_dev q = kernel_view<KIND, LIN>(q0);
   uint32_t par = 0;
   const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  // G-WFQ: the lane's help step state stays in a register for the run
+  const bool own_help = KIND == GQ_WFQ && g < q.max_threads;
+  uint32_t help = own_help ? wfq::help_load(q, (uint32_t)g) : 0;
   // per-lane counts never exceed `ops` (< 2^32): 32-bit registers suffice
   MixTally t;
   for (uint32_t r = 0; r < ops; r++) {
@@ -545,7 +554,7 @@ __device__ __forceinline__ void mix_group_body(const gq_dev& q0, uint64_t seed, 
     const uint64_t t0 = REC ? stamp() : 0;
     uint64_t v = is_enq ? ((g << 32) | (uint64_t)(t.ok_e + 1)) : 0;
     const int s = gq_group_op_k<KIND>(q, is_enq ? ROLE_ENQ : ROLE_DEQ, v, (uint32_t)g, t.cf, lds,
-                                      par);
+                                      par, KIND == GQ_WFQ ? &help : nullptr);
     if (is_enq) {
       t.enq(s, v);
     } else {
@@ -555,6 +564,7 @@ __device__ __forceinline__ void mix_group_body(const gq_dev& q0, uint64_t seed, 
     if (REC) rec.put(g, r, is_enq ? 0 : 1, s, v, t0, end_stamp(q));
   }
   if (REC && rec.h.count) rec.h.count[g] = ops;
+  if (own_help) wfq::help_store(q, (uint32_t)g, help);
   if (lane_enq) lane_enq[g] = t.ok_e;
   t.flush_group(counts, q.stats, g, acc);
 }
