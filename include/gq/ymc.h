@@ -174,16 +174,19 @@ __device__ __forceinline__ uint64_t help_enq(const Q& y, Handle* h, const Cell& 
 
 // ---- enqueue -------------------------------------------------------------------
 // `first`: a T ticket already reserved for this attempt (workgroup
-// aggregation), or GROUP_NONE.
-__device__ __forceinline__ bool enq_fast(const Q& y, uint64_t v, uint64_t& id,
-                                         uint64_t first = GROUP_NONE) {
+// aggregation), or GROUP_NONE.  Returns ENQ_DONE when v is in cell `first`
+// (or the next T cell), ENQ_RETRY when that cell was lost to a dequeuer (id
+// = the cell), ENQ_NO_POOL when the pool is exhausted (error latched).
+enum EnqFast { ENQ_RETRY = 0, ENQ_DONE = 1, ENQ_NO_POOL = 2 };
+__device__ __forceinline__ int enq_fast(const Q& y, uint64_t v, uint64_t& id,
+                                        uint64_t first = GROUP_NONE) {
   const uint64_t i = first != GROUP_NONE ? first : wave_faa(y.T, 1);
   Cell c;
-  if (!cell(y, i, c)) return true;  // pool exhausted: error latched, give up
+  if (!cell(y, i, c)) return ENQ_NO_POOL;
   uint64_t e = BOT;
-  if (cas(c.val, e, v)) return true;
+  if (cas(c.val, e, v)) return ENQ_DONE;
   id = i;
-  return false;
+  return ENQ_RETRY;
 }
 
 // Returns false when the request was abandoned (pool exhausted or a
@@ -223,8 +226,9 @@ __device__ __forceinline__ int enqueue_impl(const Q& y, const gq_dev& q, uint64_
   // attempt took (patience 0 means "one attempt, then the slow path").
   const uint32_t pat = y.patience_enq ? y.patience_enq : 1;
   for (uint32_t p = 0; p < pat; p++) {
-    if (enq_fast(y, v, id, p == 0 ? first : GROUP_NONE))
-      return ld(y.err) ? GQ_ERR_POOL_EXHAUSTED : GQ_OK;
+    const int r = enq_fast(y, v, id, p == 0 ? first : GROUP_NONE);
+    if (r == ENQ_DONE) return GQ_OK;  // the value is in its cell
+    if (r == ENQ_NO_POOL) return GQ_ERR_POOL_EXHAUSTED;
     cf++;
   }
   faa(y.stats + S_SLOW, 1ull);

@@ -583,8 +583,9 @@ __global__ __launch_bounds__(1024) void k_mix_group(gq_dev q, uint64_t seed, uin
 // most 64 VGPRs; it needs 67 otherwise, with a few bytes spilled at the cap):
 // the sweep's largest grid, 2^19 lanes, is then resident all at once instead
 // of in two rounds of workgroups (measured 2.41 -> 2.21 ms per 2^26 ops).
-// G-WFQ and G-WFQ-YMC need 100-123 VGPRs; capped, their spills cost more than
-// the second round of workgroups (2.74 -> 3.32 ms and 2.14 -> 2.53 ms).
+// G-WFQ and G-WFQ-YMC need 100-126 VGPRs; capped at 64 (272 and 168 bytes of
+// spills per lane), their 2^19 resident lanes are slower than 2^18 lanes at 4
+// wavefronts per SIMD (2.16 -> 2.84 ms and 1.72 -> 2.12 ms).
 template <bool REC, bool LIN>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_mix_group_lfq(
     gq_dev q, uint64_t seed, uint32_t ops, uint64_t* counts, uint32_t* lane_enq, Rec rec) {
