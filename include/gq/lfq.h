@@ -20,6 +20,10 @@ namespace lfq {
 
 constexpr uint32_t BOT = 0xFFFFFFFFu;   // empty slot
 constexpr uint32_t BOTC = 0xFFFFFFFEu;  // consumed slot
+// Looks a dequeuer takes at an entry whose enqueuer holds the ticket but has
+// not installed yet (see ring_deq).
+constexpr uint32_t DEQ_WAIT_POLLS = 64;
+
 // Result of an inner dequeue stopped by the fail-safe bound (error latched);
 // never a valid index (indices are below n <= 2^30).
 constexpr uint32_t GAVE_UP = 0xFFFFFFFDu;
@@ -196,6 +200,18 @@ __device__ __forceinline__ uint32_t ring_deq(const Ring& r, uint32_t& cas_fail, 
     const uint32_t c = r.cycle_of(h);
     uint64_t* p = r.at(r.slot_of(h));
     uint64_t e = ld(p);
+    // The entry is still from an older cycle but Tail shows ticket h handed
+    // to an enqueuer, whose install follows its Tail increment closely: look
+    // at the entry a bounded number of times before marking it, rather than
+    // spoil that enqueuer's attempt (with many dequeuers polling a nearly
+    // empty queue, marking sends producer after producer back for a new
+    // ticket).  The wait is bounded, so the operation stays lock-free.
+    if (older(e_cyc(e), c) && idx_free(e_idx(e)) && ld(r.tail) > h) {
+      for (uint32_t w = 0; w < DEQ_WAIT_POLLS && older(e_cyc(e), c) && idx_free(e_idx(e)); w++) {
+        pause(1);
+        e = ld(p);
+      }
+    }
     while (true) {
       if (e_cyc(e) == c && !idx_free(e_idx(e))) {
         const uint64_t x = (uint64_t)(e_idx(e) ^ BOTC);
