@@ -456,6 +456,12 @@ struct MixTally {
   // few words (one L2 line) for a tenth of a G-WFQ launch.
   __device__ __forceinline__ void flush_group(uint64_t* counts, uint64_t* stats, uint64_t g,
                                               uint64_t* acc) const {
+    add_to(acc, g);
+    __syncthreads();
+    flush_acc(acc, counts, stats);
+  }
+  // This wavefront's sums (all its lanes present) added into the LDS words.
+  __device__ __forceinline__ void add_to(uint64_t* acc, uint64_t g) const {
     uint64_t s1e, s2e;
     token_sums(g, ok_e, s1e, s2e);
     const uint64_t v[9] = {ok_e, ok_d, full, empty, s1d, s2d, s1e, s2e, cf};
@@ -465,7 +471,10 @@ struct MixTally {
       const uint64_t w = wave_sum(v[i]);
       if (lead && w) atomicAdd((unsigned long long*)&acc[i], (unsigned long long)w);
     }
-    __syncthreads();
+  }
+  // The workgroup's LDS sums to the device words (after a barrier).
+  __device__ __forceinline__ static void flush_acc(const uint64_t* acc, uint64_t* counts,
+                                                   uint64_t* stats) {
     if (threadIdx.x < 9 && acc[threadIdx.x])
       faa(threadIdx.x < 8 ? counts + threadIdx.x : stats + S_CAS_FAIL, acc[threadIdx.x]);
   }
@@ -500,9 +509,9 @@ __device__ __forceinline__ gq_dev kernel_view(const gq_dev& q) {
 }
 
 template <int KIND, bool REC>
-__device__ __forceinline__ void mix_lane(const gq_dev& q, uint64_t g, uint32_t tid, uint64_t seed,
-                                         uint32_t ops, uint64_t* counts, uint32_t* lane_enq,
-                                         const Rec& rec) {
+__device__ __forceinline__ MixTally mix_lane(const gq_dev& q, uint64_t g, uint32_t tid,
+                                             uint64_t seed, uint32_t ops, uint32_t* lane_enq,
+                                             const Rec& rec) {
   MixTally t;
   for (uint32_t r = 0; r < ops; r++) {
     const bool is_enq = (splitmix64(seed, (g << 32) | r) >> 63) == 0;
@@ -523,14 +532,18 @@ __device__ __forceinline__ void mix_lane(const gq_dev& q, uint64_t g, uint32_t t
   }
   if (REC && rec.h.count) rec.h.count[g] = ops;
   if (lane_enq) lane_enq[g] = t.ok_e;
-  t.flush(counts, q.stats, g);
+  return t;
 }
 
 template <int KIND, bool REC>
 __global__ __launch_bounds__(256) void k_mix(gq_dev q, uint64_t seed, uint32_t ops,
                                              uint64_t* counts, uint32_t* lane_enq, Rec rec) {
+  __shared__ uint64_t acc[9];
+  if (threadIdx.x < 9) acc[threadIdx.x] = 0;
+  __syncthreads();
   const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  mix_lane<KIND, REC>(q, g, (uint32_t)g, seed, ops, counts, lane_enq, rec);
+  const MixTally t = mix_lane<KIND, REC>(q, g, (uint32_t)g, seed, ops, lane_enq, rec);
+  t.flush_group(counts, q.stats, g, acc);
 }
 
 // The same workload with workgroup-aggregated first tickets: every lane of
@@ -603,11 +616,22 @@ template <int KIND, bool REC>
 __global__ __launch_bounds__(256) void k_multi_mix(const gq_dev* qs, const uint32_t* wave_q,
                                                    const uint32_t* q_lane0, const uint64_t* seed,
                                                    uint32_t ops, uint64_t* counts, Rec rec) {
+  __shared__ uint64_t acc[9];
+  if (threadIdx.x < 9) acc[threadIdx.x] = 0;
+  __syncthreads();
   const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   const uint32_t qi = __builtin_amdgcn_readfirstlane(wave_q[g / 64]);
   const gq_dev q = qs[qi];
   const uint32_t tid = (uint32_t)(g - q_lane0[qi]);
-  mix_lane<KIND, REC>(q, g, tid, ld(seed), ops, counts + 8 * (uint64_t)qi, nullptr, rec);
+  const MixTally t = mix_lane<KIND, REC>(q, g, tid, ld(seed), ops, nullptr, rec);
+  // The wavefronts of the workgroup's first queue (all of them unless the
+  // workgroup straddles queues) sum into LDS and flush once; the others flush
+  // their own sums.
+  const uint32_t q0 = __builtin_amdgcn_readfirstlane(wave_q[blockIdx.x * (blockDim.x / 64)]);
+  if (qi == q0) t.add_to(acc, g);
+  else t.flush(counts + 8 * (uint64_t)qi, q.stats, g);
+  __syncthreads();
+  MixTally::flush_acc(acc, counts + 8 * (uint64_t)q0, qs[q0].stats);
 }
 
 __global__ void k_seed(uint64_t* seed, uint64_t value, uint32_t bump) {
