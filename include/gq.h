@@ -103,7 +103,7 @@ typedef struct gq_ring_view {
     int64_t *threshold;        /* signed empty-detection counter              */
     void *records;             /* G-WFQ per-lane request records, else NULL   */
     uint64_t *owner;           /* G-WFQ per-slot installer hints, else NULL   */
-    uint8_t *hint;             /* G-WFQ per-lane "last dequeue found it empty"
+    uint8_t *hint;             /* G-LFQ, G-WFQ per-lane "last dequeue found it empty"
                                   bytes, else NULL                            */
     uint64_t *announce;        /* G-WFQ: lane + 1 of the announced slow-path
                                   request, 0 if none (own 256-byte line)      */

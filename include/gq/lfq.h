@@ -24,6 +24,9 @@ constexpr uint32_t BOTC = 0xFFFFFFFEu;  // consumed slot
 // not installed yet (see ring_deq).
 constexpr uint32_t DEQ_WAIT_POLLS = 64;
 
+// "No lane id": the caller keeps no per-lane state (no empty hint).
+constexpr uint32_t NO_LANE = 0xFFFFFFFFu;
+
 // Result of an inner dequeue stopped by the fail-safe bound (error latched);
 // never a valid index (indices are below n <= 2^30).
 constexpr uint32_t GAVE_UP = 0xFFFFFFFDu;
@@ -51,6 +54,7 @@ struct Ring {
   uint64_t* head;
   uint64_t* tail;
   int64_t* thr;
+  uint8_t* hint;      // per-lane empty hints (see ring_deq), or nullptr
   uint32_t log2_2n;   // log2(2n)
   uint32_t log2_L;    // entries per line (remap mode)
   uint32_t mode;      // gq_slot_mode
@@ -90,6 +94,7 @@ __device__ __forceinline__ Ring make_ring(const gq_ring_view& v, const gq_dev& q
   r.head = v.head;
   r.tail = v.tail;
   r.thr = v.threshold;
+  r.hint = v.hint;
   r.log2_2n = q.log2_cap + 1;
   r.log2_L = r.log2_2n < 4 ? r.log2_2n : 4;
   r.mode = q.slot_mode;
@@ -168,9 +173,16 @@ __device__ __forceinline__ bool ring_enq(const Ring& r, uint32_t idx, uint32_t& 
 // aggregation; the caller checked Threshold before reserving it).  It is
 // always used: a Head ticket that no dequeuer visits could let an enqueuer
 // install behind Head, where no later ticket reaches the item.
+// `lane`: the caller's lane id below max_threads, or NO_LANE.  A lane whose
+// last dequeue here answered EMPTY through the look below keeps looking
+// before it takes a ticket, even after an install has reset Threshold (one
+// byte per lane, cleared when the lane takes a ticket): without it, every
+// polling lane takes a ticket at each install, and all but one of them mark
+// a slot and send Tail after them.
 template <bool ACQUIRE>
 __device__ __forceinline__ uint32_t ring_deq(const Ring& r, uint32_t& cas_fail, uint64_t* err,
-                                             uint64_t first = GROUP_NONE) {
+                                             uint64_t first = GROUP_NONE,
+                                             uint32_t lane = NO_LANE) {
   for (uint32_t spin = 0;; spin++) {
     if (spin_out(spin, err)) {
       latch_error(err, (uint64_t)(-GQ_ERR_DEVICE));
@@ -187,13 +199,18 @@ __device__ __forceinline__ uint32_t ring_deq(const Ring& r, uint32_t& cas_fail, 
       // install, so the queue may be nearly empty -- look before taking a
       // ticket.  (On a queue that keeps items, the look would only add two
       // loads on the hottest lines.)
-      if (th < r.thr_reset) {
+      const bool hinted = lane != NO_LANE && r.hint && r.hint[lane] != 0;
+      if (th < r.thr_reset || hinted) {
         const uint64_t avail = poll_avail(r.head, r.tail, 0);
-        if (avail == 0) return BOT;
+        if (avail == 0) {
+          if (lane != NO_LANE && r.hint && !hinted) r.hint[lane] = 1;
+          return BOT;
+        }
         if (lane_rank(active_mask()) >= avail) {  // bounded grab: look again
           pause(1);
           continue;
         }
+        if (hinted) r.hint[lane] = 0;  // the lane takes a ticket
       }
       h = wave_faa(r.head, 1);
     }
@@ -298,12 +315,13 @@ __device__ __forceinline__ uint64_t payload_get(const gq_dev& q, uint32_t idx) {
 __device__ __forceinline__ void count_drop(const gq_dev& q) { faa(q.stats + S_DROP, 1ull); }
 
 template <bool FENCED>
-__device__ __forceinline__ int enqueue_impl(const gq_dev& q, uint64_t item, uint32_t& cas_fail) {
+__device__ __forceinline__ int enqueue_impl(const gq_dev& q, uint64_t item, uint32_t& cas_fail,
+                                            uint32_t lane) {
   const Ring fq = make_ring(q.fq, q);
   const Ring aq = make_ring(q.aq, q);
   // The payload write below depends on idx, and the previous holder of idx
   // finished reading the cell before releasing idx into fq: no acquire needed.
-  const uint32_t idx = ring_deq<false>(fq, cas_fail, q.err);
+  const uint32_t idx = ring_deq<false>(fq, cas_fail, q.err, GROUP_NONE, lane);
   if (idx == BOT) return GQ_FULL;
   if (idx >= q.capacity) {  // GAVE_UP; guards the payload array
     latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
@@ -319,10 +337,11 @@ __device__ __forceinline__ int enqueue_impl(const gq_dev& q, uint64_t item, uint
 }
 
 template <bool FENCED>
-__device__ __forceinline__ int dequeue_impl(const gq_dev& q, uint64_t* item, uint32_t& cas_fail) {
+__device__ __forceinline__ int dequeue_impl(const gq_dev& q, uint64_t* item, uint32_t& cas_fail,
+                                            uint32_t lane) {
   const Ring aq = make_ring(q.aq, q);
   const Ring fq = make_ring(q.fq, q);
-  const uint32_t idx = ring_deq<FENCED>(aq, cas_fail, q.err);
+  const uint32_t idx = ring_deq<FENCED>(aq, cas_fail, q.err, GROUP_NONE, lane);
   if (idx == BOT) return GQ_EMPTY;
   if (idx >= q.capacity) {  // GAVE_UP; guards the payload array
     latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
@@ -344,7 +363,8 @@ __device__ __forceinline__ int dequeue_impl(const gq_dev& q, uint64_t* item, uin
 // (GQ_OK for ROLE_NONE).
 template <bool FENCED>
 __device__ __forceinline__ int group_op_impl(const gq_dev& q, int role, uint64_t& item,
-                                             uint32_t& cas_fail, GroupLds& s, uint32_t& par) {
+                                             uint32_t& cas_fail, GroupLds& s, uint32_t& par,
+                                             uint32_t lane) {
   const Ring fq = make_ring(q.fq, q);
   const Ring aq = make_ring(q.aq, q);
   // The Threshold test of a dequeue precedes its ticket, as in ring_deq.
@@ -352,8 +372,8 @@ __device__ __forceinline__ int group_op_impl(const gq_dev& q, int role, uint64_t
   const bool wa = role == ROLE_DEQ && ld(aq.thr) >= 0;
   uint64_t t = group_ticket(s, par, fq.head, 1, wf, aq.head, 1, wa);
   uint32_t idx = BOT;
-  if (wf) idx = ring_deq<false>(fq, cas_fail, q.err, t);
-  else if (wa) idx = ring_deq<FENCED>(aq, cas_fail, q.err, t);
+  if (wf) idx = ring_deq<false>(fq, cas_fail, q.err, t, lane);
+  else if (wa) idx = ring_deq<FENCED>(aq, cas_fail, q.err, t, lane);
   int st = role == ROLE_ENQ ? GQ_FULL : role == ROLE_DEQ ? GQ_EMPTY : GQ_OK;
   if (idx != BOT && idx >= q.capacity) {  // GAVE_UP; guards the payload array
     latch_error(q.err, (uint64_t)(-GQ_ERR_DEVICE));
@@ -379,20 +399,25 @@ __device__ __forceinline__ int group_op_impl(const gq_dev& q, int role, uint64_t
   return st;
 }
 
+// `lane`: the caller's lane id, if it is below max_threads (its empty hints,
+// see ring_deq), else NO_LANE.
 __device__ __forceinline__ int group_op(const gq_dev& q, int role, uint64_t& item,
-                                        uint32_t& cas_fail, GroupLds& s, uint32_t& par) {
-  return (q.flags & GQ_OPT_FENCED) ? group_op_impl<true>(q, role, item, cas_fail, s, par)
-                                   : group_op_impl<false>(q, role, item, cas_fail, s, par);
+                                        uint32_t& cas_fail, GroupLds& s, uint32_t& par,
+                                        uint32_t lane = NO_LANE) {
+  return (q.flags & GQ_OPT_FENCED) ? group_op_impl<true>(q, role, item, cas_fail, s, par, lane)
+                                   : group_op_impl<false>(q, role, item, cas_fail, s, par, lane);
 }
 
-__device__ __forceinline__ int enqueue(const gq_dev& q, uint64_t item, uint32_t& cas_fail) {
-  return (q.flags & GQ_OPT_FENCED) ? enqueue_impl<true>(q, item, cas_fail)
-                                   : enqueue_impl<false>(q, item, cas_fail);
+__device__ __forceinline__ int enqueue(const gq_dev& q, uint64_t item, uint32_t& cas_fail,
+                                       uint32_t lane = NO_LANE) {
+  return (q.flags & GQ_OPT_FENCED) ? enqueue_impl<true>(q, item, cas_fail, lane)
+                                   : enqueue_impl<false>(q, item, cas_fail, lane);
 }
 
-__device__ __forceinline__ int dequeue(const gq_dev& q, uint64_t* item, uint32_t& cas_fail) {
-  return (q.flags & GQ_OPT_FENCED) ? dequeue_impl<true>(q, item, cas_fail)
-                                   : dequeue_impl<false>(q, item, cas_fail);
+__device__ __forceinline__ int dequeue(const gq_dev& q, uint64_t* item, uint32_t& cas_fail,
+                                       uint32_t lane = NO_LANE) {
+  return (q.flags & GQ_OPT_FENCED) ? dequeue_impl<true>(q, item, cas_fail, lane)
+                                   : dequeue_impl<false>(q, item, cas_fail, lane);
 }
 
 }  // namespace lfq

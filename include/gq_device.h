@@ -17,9 +17,11 @@
  *     wave-batched fast path, Section III-B, Lemma 1).
  *   - No barrier is used inside; no __syncthreads around the calls is needed.
  *   - tid identifies the calling lane among all lanes that use the queue
- *     concurrently: unique and < gq_dev.max_threads.  G-LFQ ignores it;
- *     G-WFQ and G-WFQ-YMC index their per-lane request records with it
- *     (Section III-C, "Data structure"; Section III-A).
+ *     concurrently: unique and < gq_dev.max_threads.  G-WFQ and G-WFQ-YMC
+ *     index their per-lane request records with it (Section III-C, "Data
+ *     structure"; Section III-A); all three keep a per-lane "last dequeue
+ *     found the queue empty" byte with it (G-LFQ skips it for tid >=
+ *     max_threads).
  *   - Wait-freedom of G-WFQ and G-WFQ-YMC holds while every participating
  *     lane's wavefront stays resident and is fairly scheduled (Section III-C,
  *     Theorem "GPU-resident wait-freedom"); G-LFQ is lock-free.
@@ -41,8 +43,7 @@ template <int KIND>
 __device__ __forceinline__ int gq_enqueue_k(const gq_dev& q, uint64_t item, uint32_t tid,
                                             uint32_t& cas_fail) {
   if constexpr (KIND == GQ_LFQ) {
-    (void)tid;
-    return gq::lfq::enqueue(q, item, cas_fail);
+    return gq::lfq::enqueue(q, item, cas_fail, tid < q.max_threads ? tid : gq::lfq::NO_LANE);
   } else if constexpr (KIND == GQ_WFQ) {
     return gq::wfq::enqueue(q, item, tid, cas_fail);
   } else {
@@ -54,8 +55,7 @@ template <int KIND>
 __device__ __forceinline__ int gq_dequeue_k(const gq_dev& q, uint64_t* item, uint32_t tid,
                                             uint32_t& cas_fail) {
   if constexpr (KIND == GQ_LFQ) {
-    (void)tid;
-    return gq::lfq::dequeue(q, item, cas_fail);
+    return gq::lfq::dequeue(q, item, cas_fail, tid < q.max_threads ? tid : gq::lfq::NO_LANE);
   } else if constexpr (KIND == GQ_WFQ) {
     return gq::wfq::dequeue(q, item, tid, cas_fail);
   } else {
@@ -83,9 +83,9 @@ __device__ __forceinline__ int gq_group_op_k(const gq_dev& q, int role, uint64_t
                                              uint32_t tid, uint32_t& cas_fail, gq::GroupLds& lds,
                                              uint32_t& par, uint32_t* help = nullptr) {
   if constexpr (KIND == GQ_LFQ) {
-    (void)tid;
     (void)help;
-    return gq::lfq::group_op(q, role, item, cas_fail, lds, par);
+    return gq::lfq::group_op(q, role, item, cas_fail, lds, par,
+                             tid < q.max_threads ? tid : gq::lfq::NO_LANE);
   } else if constexpr (KIND == GQ_WFQ) {
     return gq::wfq::group_op(q, role, item, tid, cas_fail, lds, par, help);
   } else {

@@ -129,7 +129,9 @@ gq_status plan(gq_kind kind, uint64_t n, uint32_t w, uint32_t k, const gq_option
     off = align_up(off + 2 * n * 8, 4096);
     L->help = off;
     off = align_up(off + (uint64_t)k * 4, 4096);
-    L->hint = off;  // k bytes for aq, then k for fq
+  }
+  if (kind == GQ_WFQ || kind == GQ_LFQ) {
+    L->hint = off;  // per-lane empty hints: k bytes for aq, then k for fq
     off = align_up(off + 2 * (uint64_t)k, 4096);
   }
   if (kind == GQ_WFQ_YMC) {
@@ -173,6 +175,11 @@ __device__ void init_lfq_range(const gq_dev& q, uint64_t g0, uint64_t stride) {
     st(q.err, 0ull);
     for (int s = 0; s < S_NUM; s++) st(q.stats + s, 0ull);
   }
+  if (q.aq.hint)
+    for (uint64_t t = g0; t < q.max_threads; t += stride) {
+      q.aq.hint[t] = 0;
+      q.fq.hint[t] = 0;
+    }
 }
 
 __global__ void k_init_lfq(gq_dev q) {
@@ -1065,6 +1072,10 @@ static gq_dev make_dev(gq_kind kind, uint64_t capacity, uint32_t item_width,
     d.help_ctr = (uint32_t*)(buf + L.help);
     d.aq.announce = (uint64_t*)(buf + OFF_AQ_ANN);
     d.fq.announce = (uint64_t*)(buf + OFF_FQ_ANN);
+  }
+  if (kind == GQ_LFQ) {
+    d.aq.hint = (uint8_t*)(buf + L.hint);
+    d.fq.hint = (uint8_t*)(buf + L.hint) + max_threads;
   }
   d.err = (uint64_t*)(buf + OFF_ERR);
   d.stats = (uint64_t*)(buf + OFF_STATS);
