@@ -604,9 +604,7 @@ def bench_timed(gq, torch, kinds, reps=5, warmup_us=1000, window_us=5000):
     kernels (producer fractions 25/50/75 %), T = 2^9 .. 2^15 lanes in
     workgroups of 256, per-wavefront tickets, capacity 2^20 prefilled to n/2;
     Mops/s = successful operations completed in the window / window, median
-    of 5.  G-WFQ runs the balanced form only: in a split run one side can
-    outpace the other and poll an empty (or full) queue, where its slow path
-    starves (see the design notes)."""
+    of 5."""
     out = {}
     for kind in kinds:
         q = gq.Queue(kind, CAP, item_width=ITEM_BYTES, max_threads=1 << 15,
@@ -615,8 +613,6 @@ def bench_timed(gq, torch, kinds, reps=5, warmup_us=1000, window_us=5000):
         counts = torch.zeros(10, dtype=torch.int64, device="cuda")
         ctl = torch.zeros(4, dtype=torch.int64, device="cuda")
         modes = [("balanced", 50), ("split", 25), ("split", 50), ("split", 75)]
-        if kind == "wfq":
-            modes = [("balanced", 50)]
         res = {}
         for mode, pct in modes:
             key = "balanced" if mode == "balanced" else f"split{pct}"

@@ -102,9 +102,6 @@ def test_timed_history_oracle(kind, mode, pct):
     import paper_2606_01693_amd as gq
     T = torch()
     n, lanes, per_lane = 1 << 12, 4096, 2048
-    if kind == "wfq" and mode == "split":
-        pytest.skip("G-WFQ split runs poll an empty or full queue on the slow path (the "
-                    "benchmark runs G-WFQ balanced only); covered by the C3 runs instead")
     print(f"[case] timed history kind={kind} mode={mode} pct={pct}", flush=True)
     q = gq.Queue(kind, n, item_width=8, max_threads=lanes,
                  ymc_pool_cells=(1 << 26) if kind == "ymc" else 0)
