@@ -201,18 +201,53 @@ __device__ __forceinline__ uint32_t ring_deq(const Ring& r, uint32_t& cas_fail, 
       // loads on the hottest lines.)
       const bool hinted = lane != NO_LANE && r.hint && r.hint[lane] != 0;
       if (th < r.thr_reset || hinted) {
-        const uint64_t avail = poll_avail(r.head, r.tail, 0);
+        // Bounded grab: with a entries between Head and Tail, the wavefront
+        // takes at most a tickets (its other lanes look again).  A full
+        // wavefront takes them with one CAS that moves Head from the value
+        // it read, so no ticket of the grab lies past Tail: with thousands
+        // of polling lanes, FAA tickets taken on a seen entry overshoot Tail
+        // by all but one wavefront's share, and each overshooting ticket
+        // marks a slot an enqueuer is about to use.  A partial wavefront
+        // takes FAA tickets: its overshoot is at most its few lanes, while
+        // hundreds of such wavefronts racing one CAS each would win one per
+        // round trip.  A lost CAS looks again.
+        const uint64_t hh = read_first_lane(ld(r.head));
+        keep(hh);
+        wait_mem();
+        const uint64_t tt = read_first_lane(ld(r.tail));
+        const uint64_t avail = tt > hh ? tt - hh : 0;
         if (avail == 0) {
           if (lane != NO_LANE && r.hint && !hinted) r.hint[lane] = 1;
           return BOT;
         }
-        if (lane_rank(active_mask()) >= avail) {  // bounded grab: look again
-          pause(1);
-          continue;
+        const uint64_t mask = active_mask();
+        const uint32_t rank = lane_rank(mask);
+        const uint64_t act = (uint64_t)__popcll(mask);
+        const uint64_t want = avail < act ? avail : act;
+        if (act == 64) {
+          uint64_t won = 0;
+          if (rank == 0) {
+            uint64_t e = hh;
+            won = cas(r.head, e, hh + want) ? 1 : 0;
+          }
+          won = read_first_lane(won);
+          if (!won || rank >= want) {
+            pause(1);
+            continue;
+          }
+          if (hinted) r.hint[lane] = 0;  // the lane takes a ticket
+          h = hh + rank;
+        } else {
+          if (rank >= want) {
+            pause(1);
+            continue;
+          }
+          if (hinted) r.hint[lane] = 0;
+          h = wave_faa(r.head, 1);
         }
-        if (hinted) r.hint[lane] = 0;  // the lane takes a ticket
+      } else {
+        h = wave_faa(r.head, 1);
       }
-      h = wave_faa(r.head, 1);
     }
     const uint32_t c = r.cycle_of(h);
     uint64_t* p = r.at(r.slot_of(h));
