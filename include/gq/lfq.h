@@ -205,12 +205,12 @@ __device__ __forceinline__ uint32_t ring_deq(const Ring& r, uint32_t& cas_fail, 
         // takes at most a tickets (its other lanes look again).  A full
         // wavefront takes them with one CAS that moves Head from the value
         // it read, so no ticket of the grab lies past Tail: with thousands
-        // of polling lanes, FAA tickets taken on a seen entry overshoot Tail
-        // by all but one wavefront's share, and each overshooting ticket
-        // marks a slot an enqueuer is about to use.  A partial wavefront
-        // takes FAA tickets: its overshoot is at most its few lanes, while
-        // hundreds of such wavefronts racing one CAS each would win one per
-        // round trip.  A lost CAS looks again.
+        // of polling lanes, FAA tickets taken on the seen entries overshoot
+        // Tail by all but one wavefront's share, and each overshooting
+        // ticket marks a slot an enqueuer is about to use.  A partial
+        // wavefront takes FAA tickets: its overshoot is at most its few
+        // lanes, while hundreds of such wavefronts racing one CAS each would
+        // win one per round trip.  A lost CAS looks again.
         const uint64_t hh = read_first_lane(ld(r.head));
         keep(hh);
         wait_mem();

@@ -616,6 +616,18 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
   mix_group_body<GQ_LFQ, REC, LIN>(q, seed, ops, counts, lane_enq, rec, lds, acc);
 }
 
+// Dequeue for the level-synchronous BFS loops (queue BFS, serving teams).
+// A level's dequeues end at its first EMPTY and nothing is enqueued into the
+// level's queue meanwhile, so G-LFQ's per-lane empty hints (for lanes that
+// poll a queue others refill) would only add a look before every lane's
+// first ticket two levels later: G-LFQ is called without a lane id.
+template <int KIND>
+__device__ __forceinline__ int level_dequeue(const gq_dev& q, uint64_t* v, uint32_t tid,
+                                             uint32_t& cf) {
+  if constexpr (KIND == GQ_LFQ) return lfq::dequeue(q, v, cf);
+  else return gq_dequeue_k<KIND>(q, v, tid, cf);
+}
+
 // Many independent queues in one launch: wavefront w works on queue
 // wave_q[w]; lane ids inside a queue start at q_lane0[queue].  The seed is
 // read from device memory so that a captured graph can advance it.
